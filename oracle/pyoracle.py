@@ -1,0 +1,196 @@
+"""ctypes wrapper around the C oracle (test infrastructure only).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg use this
+module.  All vectors are float64 numpy arrays in natural order
+i = ix + nx*(iy + ny*iz).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+        L.ora_create.restype = vp
+        L.ora_create.argtypes = [i32, i32, i32, i32, i32, vp]
+        L.ora_destroy.argtypes = [vp]
+        L.ora_n.restype = i64
+        L.ora_n.argtypes = [vp, i32]
+        L.ora_nnz.restype = i64
+        L.ora_nnz.argtypes = [vp, i32]
+        L.ora_ncolours.restype = i32
+        L.ora_ncolours.argtypes = [vp, i32]
+        L.ora_get_crs.argtypes = [vp, i32, vp, vp, vp]
+        L.ora_get_colours.argtypes = [vp, i32, vp]
+        L.ora_get_f2c.argtypes = [vp, i32, vp]
+        L.ora_spmv.argtypes = [vp, i32, vp, vp]
+        L.ora_colour_pass.argtypes = [vp, i32, i32, vp, vp]
+        L.ora_sgs.argtypes = [vp, i32, vp, vp]
+        L.ora_restrict.argtypes = [vp, i32, vp, vp, vp]
+        L.ora_prolong_add.argtypes = [vp, i32, vp, vp]
+        L.ora_vcycle.argtypes = [vp, i32, vp, vp]
+        L.ora_vcycle32.argtypes = [vp, vp, vp]
+        L.ora_sgs32.argtypes = [vp, i32, vp, vp]
+        L.ora_pcg.restype = i32
+        L.ora_pcg.argtypes = [vp, vp, vp, i32, dbl, i32, vp, vp]
+        L.ora_theta_grad.argtypes = [i64, vp, vp, vp, vp]
+        L.ora_dot.restype = dbl
+        L.ora_dot.argtypes = [i64, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+class Oracle:
+    """One level hierarchy of the MG-PCG problem, built by the C oracle."""
+
+    def __init__(self, nx, ny, nz, levels=4, colour_order=0, theta=None):
+        self.dims = (nx, ny, nz)
+        self.levels = levels
+        self.colour_order = colour_order
+        th = None
+        if theta is not None:
+            th = _f64(theta)
+            assert th.size == nx * ny * nz
+        self._h = lib().ora_create(nx, ny, nz, levels, colour_order, None if th is None else _p(th))
+        if not self._h:
+            raise ValueError(f"oracle: invalid problem {nx}x{ny}x{nz} levels={levels}")
+
+    def close(self):
+        if self._h:
+            lib().ora_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- introspection
+    def n(self, level=0):
+        return lib().ora_n(self._h, level)
+
+    def nnz(self, level=0):
+        return lib().ora_nnz(self._h, level)
+
+    def ncolours(self, level=0):
+        return lib().ora_ncolours(self._h, level)
+
+    def level_dims(self, level):
+        return tuple(d >> level for d in self.dims)
+
+    def crs(self, level=0):
+        n, nnz = self.n(level), self.nnz(level)
+        rp = np.zeros(n + 1, np.int64)
+        col = np.zeros(nnz, np.int32)
+        val = np.zeros(nnz, np.float64)
+        lib().ora_get_crs(self._h, level, _p(rp), _p(col), _p(val))
+        return rp, col, val
+
+    def dense(self, level=0):
+        rp, col, val = self.crs(level)
+        n = self.n(level)
+        A = np.zeros((n, n))
+        for i in range(n):
+            A[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+        return A
+
+    def colours(self, level=0):
+        c = np.zeros(self.n(level), np.int32)
+        lib().ora_get_colours(self._h, level, _p(c))
+        return c
+
+    def f2c(self, level=0):
+        m = np.zeros(self.n(level + 1), np.int64)
+        lib().ora_get_f2c(self._h, level, _p(m))
+        return m
+
+    # --- building blocks
+    def spmv(self, x, level=0):
+        x = _f64(x)
+        y = np.zeros(self.n(level))
+        lib().ora_spmv(self._h, level, _p(x), _p(y))
+        return y
+
+    def colour_pass(self, k, r, z, level=0):
+        r = _f64(r)
+        z = _f64(z).copy()
+        lib().ora_colour_pass(self._h, level, k, _p(r), _p(z))
+        return z
+
+    def sgs(self, r, z, level=0):
+        r = _f64(r)
+        z = _f64(z).copy()
+        lib().ora_sgs(self._h, level, _p(r), _p(z))
+        return z
+
+    def sgs32(self, r, z, level=0):
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        z = np.ascontiguousarray(z, dtype=np.float32).copy()
+        lib().ora_sgs32(self._h, level, _p(r), _p(z))
+        return z
+
+    def restrict(self, r, z, level=0):
+        r, z = _f64(r), _f64(z)
+        rc = np.zeros(self.n(level + 1))
+        lib().ora_restrict(self._h, level, _p(r), _p(z), _p(rc))
+        return rc
+
+    def prolong_add(self, zc, z, level=0):
+        zc = _f64(zc)
+        z = _f64(z).copy()
+        lib().ora_prolong_add(self._h, level, _p(zc), _p(z))
+        return z
+
+    def vcycle(self, r, level=0):
+        r = _f64(r)
+        z = np.zeros(self.n(level))
+        lib().ora_vcycle(self._h, level, _p(r), _p(z))
+        return z
+
+    def vcycle32(self, r):
+        r = _f64(r)
+        z = np.zeros(self.n(0))
+        lib().ora_vcycle32(self._h, _p(r), _p(z))
+        return z
+
+    def pcg(self, b, x0=None, max_iters=50, tol=0.0, precond=1):
+        """Returns (x, history, iters, status)."""
+        b = _f64(b)
+        x = np.zeros(self.n(0)) if x0 is None else _f64(x0).copy()
+        hist = np.zeros(max(max_iters, 1))
+        it = C.c_int(0)
+        st = lib().ora_pcg(self._h, _p(b), _p(x), max_iters, float(tol), precond,
+                           _p(hist), C.byref(it))
+        return x, hist[: it.value].copy(), it.value, st
+
+    @staticmethod
+    def theta_grad(lam, x, theta):
+        lam, x, theta = _f64(lam), _f64(x), _f64(theta)
+        g = np.zeros(lam.size)
+        lib().ora_theta_grad(lam.size, _p(lam), _p(x), _p(theta), _p(g))
+        return g
+
+    @staticmethod
+    def dot(a, b):
+        a, b = _f64(a), _f64(b)
+        return lib().ora_dot(a.size, _p(a), _p(b))

@@ -1,0 +1,380 @@
+"""Pins of the CPU oracle against what the problem and the mathematics fix.
+
+None of these compares the oracle with itself: closed forms, invariants,
+special cases that reduce to textbook algorithms, and brute force from the
+dense references in bruteforce.py.
+"""
+import numpy as np
+import pytest
+
+import bruteforce as bf
+from oracle import Oracle
+
+SMALL_DIMS = [(2, 2, 2), (3, 3, 3), (4, 4, 4), (6, 5, 4), (7, 4, 5), (5, 3, 2)]
+
+
+# ---------------------------------------------------------------- matrix (Sec. II-A/B)
+
+@pytest.mark.parametrize("dims", SMALL_DIMS + [(16, 16, 16), (24, 32, 48)])
+def test_nnz_closed_form(dims):
+    nx, ny, nz = dims
+    o = Oracle(nx, ny, nz, levels=1)
+    assert o.nnz() == (3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2)
+
+
+def test_nnz_per_level_16cubed():
+    o = Oracle(16, 16, 16, levels=4)
+    assert [o.n(l) for l in range(4)] == [4096, 512, 64, 8]
+    assert [o.nnz(l) for l in range(4)] == [97336, 10648, 1000, 64]
+
+
+@pytest.mark.parametrize("dims", SMALL_DIMS)
+def test_matrix_equals_chebyshev_stencil(dims):
+    o = Oracle(*dims, levels=1)
+    assert np.array_equal(o.dense(), bf.dense_stencil(*dims))
+
+
+@pytest.mark.parametrize("dims", [(6, 5, 4), (8, 8, 8)])
+def test_matrix_symmetric_rowsums_rhs(dims):
+    o = Oracle(*dims, levels=1)
+    rp, col, val = o.crs()
+    A = o.dense()
+    assert np.array_equal(A, A.T)
+    # columns ascending within every row (CRS order used for the sums)
+    for i in range(o.n()):
+        assert np.all(np.diff(col[rp[i]:rp[i + 1]]) > 0)
+    # b = A*1 gives b_i = 27 - nnz_i exactly; interior rows sum to zero
+    b = o.spmv(np.ones(o.n()))
+    nnz_row = np.diff(rp)
+    assert np.array_equal(b, 27.0 - nnz_row)
+    assert np.all(b[nnz_row == 27] == 0.0)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4), (6, 6, 6), (6, 5, 4)])
+def test_matrix_spd(dims):
+    A = Oracle(*dims, levels=1).dense()
+    np.linalg.cholesky(A)  # raises if not positive definite
+    assert np.linalg.eigvalsh(A).min() > 0
+
+
+def test_theta_diagonal():
+    rng = np.random.default_rng(0)
+    th = rng.normal(0, 0.5, 4 * 4 * 4)
+    o = Oracle(4, 4, 4, levels=3, theta=th)
+    np.testing.assert_allclose(o.dense(0), bf.dense_stencil(4, 4, 4, th), rtol=1e-15, atol=0)
+    # coarse level: theta injected at (2jx, 2jy, 2jz)
+    R = bf.injection_matrix(4, 4, 4)
+    np.testing.assert_allclose(o.dense(1), bf.dense_stencil(2, 2, 2, R @ th), rtol=1e-15, atol=0)
+    # large |theta| stays finite and correct
+    th2 = np.array([800.0, -800.0, 0.0, 30.0, -30.0, 1e-3, 5.0, -5.0])
+    o2 = Oracle(2, 2, 2, levels=1, theta=th2)
+    d = np.diag(o2.dense())
+    np.testing.assert_allclose(d, 26.0 + np.array([800.0, 0.0, np.log(2.0), 30.0 + np.log1p(np.exp(-30.0)),
+                                                   np.exp(-30.0), np.log1p(np.exp(1e-3)),
+                                                   5.0 + np.log1p(np.exp(-5.0)), np.log1p(np.exp(-5.0))]),
+                               rtol=1e-15)
+
+
+def test_invalid_problems_rejected():
+    with pytest.raises(ValueError):
+        Oracle(6, 6, 6, levels=3)  # 6 not divisible by 4
+    with pytest.raises(ValueError):
+        Oracle(0, 4, 4, levels=1)
+
+
+# ------------------------------------------------------------ colouring (Sec. III-A)
+
+def greedy_bruteforce(A):
+    n = A.shape[0]
+    col = -np.ones(n, int)
+    for i in range(n):
+        used = {col[j] for j in np.nonzero(A[i])[0] if j < i}
+        c = 0
+        while c in used:
+            c += 1
+        col[i] = c
+    return col
+
+
+@pytest.mark.parametrize("dims", SMALL_DIMS + [(8, 6, 4)])
+def test_greedy_equals_parity_code(dims):
+    o = Oracle(*dims, levels=1)
+    c = o.colours()
+    assert np.array_equal(c, greedy_bruteforce(bf.dense_stencil(*dims)))
+    assert np.array_equal(c, bf.parity_colour(*dims))
+    assert o.ncolours() == 8
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4), (16, 16, 16), (6, 5, 4)])
+def test_colouring_proper_and_balanced(dims):
+    o = Oracle(*dims, levels=1)
+    rp, col, _ = o.crs()
+    c = o.colours()
+    rows = np.repeat(np.arange(o.n()), np.diff(rp))
+    off = rows != col
+    assert not np.any(c[rows[off]] == c[col[off]])
+    if all(d % 2 == 0 for d in dims):
+        assert np.all(np.bincount(c, minlength=8) == o.n() // 8)
+
+
+def test_colour_order_reversed():
+    o0 = Oracle(4, 4, 4, levels=1, colour_order=0)
+    o1 = Oracle(4, 4, 4, levels=1, colour_order=1)
+    assert np.array_equal(o1.colours(), 7 - o0.colours())
+
+
+@pytest.mark.parametrize("dims,nc", [((4, 4, 1), 4), ((4, 1, 1), 2), ((1, 1, 1), 1), ((1, 3, 4), 4)])
+def test_colouring_flat_grids(dims, nc):
+    o = Oracle(*dims, levels=1)
+    c = o.colours()
+    assert o.ncolours() == nc
+    assert np.array_equal(c, greedy_bruteforce(bf.dense_stencil(*dims)))
+
+
+# ------------------------------------------------------- smoother (Eq. (1), Listings 2-3)
+
+@pytest.mark.parametrize("dims", [(4, 4, 4), (6, 5, 4), (3, 3, 3)])
+@pytest.mark.parametrize("order", [0, 1])
+def test_coloured_sweep_equals_sequential_gs(dims, order):
+    rng = np.random.default_rng(1)
+    o = Oracle(*dims, levels=1, colour_order=order)
+    A = o.dense()
+    n = o.n()
+    r = rng.uniform(-1, 1, n)
+    z0 = rng.uniform(-1, 1, n)
+    c = o.colours()
+    # forward pass only: colour passes 0..7 == sequential GS over rows sorted by colour
+    zf = z0.copy()
+    for k in range(o.ncolours()):
+        zf = o.colour_pass(k, r, zf)
+    zbf = bf.gs_sequential(A, r, z0, bf.colour_sorted_order(c))
+    np.testing.assert_allclose(zf, zbf, rtol=1e-13, atol=1e-15)
+    # full symmetric sweep
+    np.testing.assert_allclose(o.sgs(r, z0), bf.sgs_sequential(A, r, z0, c), rtol=1e-13, atol=1e-15)
+
+
+def test_forward_sweep_on_2cubed_is_lexicographic_gs():
+    # on 2x2x2 the colour number equals the row index, so the coloured forward
+    # pass is textbook lexicographic Gauss-Seidel
+    rng = np.random.default_rng(2)
+    o = Oracle(2, 2, 2, levels=1)
+    A = o.dense()
+    r, z0 = rng.uniform(-1, 1, 8), rng.uniform(-1, 1, 8)
+    z = z0.copy()
+    for k in range(8):
+        z = o.colour_pass(k, r, z)
+    L = np.tril(A)
+    U = A - L
+    np.testing.assert_allclose(z, np.linalg.solve(L, r - U @ z0), rtol=1e-14)
+
+
+def test_sweep_fixed_point():
+    rng = np.random.default_rng(3)
+    o = Oracle(6, 5, 4, levels=1)
+    A = o.dense()
+    zs = rng.uniform(-1, 1, o.n())
+    r = A @ zs
+    np.testing.assert_allclose(o.sgs(r, zs), zs, rtol=0, atol=1e-14)
+
+
+# ----------------------------------------------------------- transfers (Sec. II-F, III-B)
+
+def test_injection_map_and_adjointness():
+    rng = np.random.default_rng(4)
+    o = Oracle(8, 6, 4, levels=2)
+    R = bf.injection_matrix(8, 6, 4)
+    f2c = o.f2c(0)
+    assert np.array_equal(R[np.arange(R.shape[0]), f2c], np.ones(R.shape[0]))
+    np.testing.assert_array_equal(R @ R.T, np.eye(R.shape[0]))
+    # restriction of (r - A z) by the oracle equals R (r - A z)
+    A = o.dense()
+    r, z = rng.uniform(-1, 1, o.n()), rng.uniform(-1, 1, o.n())
+    np.testing.assert_allclose(o.restrict(r, z), R @ (r - A @ z), rtol=1e-15, atol=1e-15)
+    # refinement is the transpose: <R u, v> = <u, R^T v> exactly (pure copies)
+    u, v = rng.uniform(-1, 1, o.n()), rng.uniform(-1, 1, o.n(1))
+    pz = o.prolong_add(v, np.zeros(o.n()))
+    assert np.array_equal(pz, R.T @ v)
+    assert Oracle.dot(R @ u, v) == Oracle.dot(u[f2c], v)
+
+
+# ------------------------------------------------------------ V-cycle (Listing 1)
+
+def _dense_hierarchy(o):
+    As = [o.dense(l) for l in range(o.levels)]
+    cs = [o.colours(l) for l in range(o.levels)]
+    Rs = [bf.injection_matrix(*o.level_dims(l)) for l in range(o.levels - 1)]
+    return As, cs, Rs
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("dims,levels", [((4, 4, 4), 3), ((8, 8, 4), 3), ((8, 8, 8), 4)])
+def test_vcycle_equals_dense_bruteforce(dims, levels, order):
+    rng = np.random.default_rng(5)
+    o = Oracle(*dims, levels=levels, colour_order=order)
+    As, cs, Rs = _dense_hierarchy(o)
+    for _ in range(3):
+        r = rng.uniform(-1, 1, o.n())
+        np.testing.assert_allclose(o.vcycle(r), bf.vcycle_dense(As, cs, Rs, r), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_vcycle_linear_symmetric_positive(order):
+    rng = np.random.default_rng(6)
+    o = Oracle(16, 16, 16, levels=4, colour_order=order)
+    u, v = rng.uniform(-1, 1, o.n()), rng.uniform(-1, 1, o.n())
+    Mu, Mv = o.vcycle(u), o.vcycle(v)
+    np.testing.assert_allclose(o.vcycle(2.0 * u + 3.0 * v), 2.0 * Mu + 3.0 * Mv, rtol=1e-12, atol=1e-14)
+    # the symmetry test a replacement smoother must pass (Sec. III-A)
+    a, b = u @ Mv, v @ Mu
+    assert abs(a - b) <= 1e-14 * abs(a)
+    assert u @ Mu > 0 and v @ Mv > 0
+
+
+def test_restricted_residual_vanishes_under_literal_order():
+    # Greedy colour 0 is the set of all-even points, i.e. exactly the
+    # injection points, and the backward pass ends on it, so every injected
+    # equation is solved exactly by the pre-smoother: r_c = 0 up to rounding.
+    rng = np.random.default_rng(7)
+    o0 = Oracle(16, 16, 16, levels=4, colour_order=0)
+    o1 = Oracle(16, 16, 16, levels=4, colour_order=1)
+    for lvl in range(3):
+        n = o0.n(lvl)
+        r = rng.uniform(-1, 1, n)
+        z0 = o0.sgs(r, np.zeros(n), level=lvl)
+        rc0 = o0.restrict(r, z0, level=lvl)
+        assert np.linalg.norm(rc0) <= 1e-14 * np.linalg.norm(r)
+        z1 = o1.sgs(r, np.zeros(n), level=lvl)
+        rc1 = o1.restrict(r, z1, level=lvl)
+        assert np.linalg.norm(rc1) >= 1e-3 * np.linalg.norm(r[o1.f2c(lvl)])
+
+
+# ----------------------------------------------------------------- PCG (Sec. II-C)
+
+@pytest.mark.parametrize("precond", [0, 1])
+@pytest.mark.parametrize("order", [0, 1])
+def test_pcg_iterates_are_krylov_optimal(precond, order):
+    rng = np.random.default_rng(8)
+    o = Oracle(4, 4, 4, levels=3, colour_order=order)
+    A = o.dense()
+    n = o.n()
+    Minv = np.eye(n) if precond == 0 else np.stack([o.vcycle(e) for e in np.eye(n)], axis=1)
+    b = rng.uniform(-1, 1, n)
+    x0 = rng.uniform(-1, 1, n)
+    for k in range(1, 6):
+        xk, hist, it, st = o.pcg(b, x0=x0, max_iters=k, precond=precond)
+        assert it == k and st == 0
+        xopt = bf.krylov_optimal(A, Minv, b, x0, k)
+        np.testing.assert_allclose(xk, xopt, rtol=1e-9, atol=1e-11)
+        # the recursive residual history equals the true residual here
+        np.testing.assert_allclose(hist[-1], np.linalg.norm(b - A @ xk) / np.linalg.norm(b - A @ x0),
+                                   rtol=1e-8, atol=1e-14)
+
+
+def test_pcg_converges_to_ones_and_error_monotone():
+    o = Oracle(8, 8, 8, levels=4)
+    A = o.dense()
+    b = o.spmv(np.ones(o.n()))
+    prev = np.inf
+    for k in range(1, 12):
+        xk, _, _, _ = o.pcg(b, max_iters=k)
+        e = xk - 1.0
+        ea = np.sqrt(e @ A @ e)
+        assert ea <= prev * (1 + 1e-12)
+        prev = ea
+    x, hist, it, st = o.pcg(b, max_iters=200, tol=1e-13)
+    assert st == 0 and hist[-1] <= 1e-13
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(x, 1.0, rtol=0, atol=1e-11)
+
+
+def test_pcg_status_codes():
+    o = Oracle(4, 4, 4, levels=3)
+    b = o.spmv(np.ones(o.n()))
+    _, hist, it, st = o.pcg(b, max_iters=3, tol=1e-30)
+    assert st == 1 and it == 3 and hist.size == 3
+    bn = b.copy()
+    bn[3] = np.nan
+    _, _, it, st = o.pcg(bn, max_iters=5)
+    assert st == -5 and it == 0
+    _, hist, it, st = o.pcg(np.zeros(o.n()), max_iters=5)
+    assert st == 0 and it == 0
+
+
+# --------------------------------------------------------------- FP32 V-cycle
+
+def test_fp32_vcycle_close_to_fp64():
+    rng = np.random.default_rng(9)
+    o = Oracle(16, 16, 16, levels=4, colour_order=1)
+    r = rng.uniform(-1, 1, o.n())
+    z64 = o.vcycle(r)
+    z32 = o.vcycle32(r)
+    err = np.abs(z32 - z64).max() / np.abs(z64).max()
+    assert 1e-9 < err < 1e-5  # genuinely single precision, and close
+    # the FP32 sweep equals the dense sequential GS carried out in float32
+    o2 = Oracle(4, 4, 4, levels=1)
+    A32 = o2.dense().astype(np.float32)
+    rr = rng.uniform(-1, 1, 64).astype(np.float32)
+    zz = o2.sgs32(rr, np.zeros(64, np.float32))
+    ref = bf.sgs_sequential(A32.astype(np.float64), rr.astype(np.float64), np.zeros(64), o2.colours())
+    np.testing.assert_allclose(zz, ref, rtol=1e-5, atol=1e-7)
+
+
+def test_fp32_pcg_reaches_tolerance():
+    o = Oracle(16, 16, 16, levels=4)
+    b = o.spmv(np.ones(o.n()))
+    _, h64, it64, _ = o.pcg(b, max_iters=100, tol=1e-9, precond=1)
+    _, h32, it32, st = o.pcg(b, max_iters=100, tol=1e-9, precond=2)
+    assert st == 0 and h32[-1] <= 1e-9
+    assert abs(it32 - it64) <= 2
+
+
+# ------------------------------------------------------- differentiable solve
+
+def test_theta_gradient_matches_dense_autograd():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(10)
+    n = 64
+    theta = rng.normal(0, 0.5, n)
+    b = rng.uniform(-1, 1, n)
+    xt = rng.uniform(-1, 1, n)
+    o = Oracle(4, 4, 4, levels=3, theta=theta)
+    x, _, _, st = o.pcg(b, max_iters=200, tol=1e-14)
+    assert st == 0
+    lam, _, _, st = o.pcg(x - xt, max_iters=200, tol=1e-14)
+    g = Oracle.theta_grad(lam, x, theta)
+    # dense reference: autograd through a direct solve
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    A0 = torch.tensor(bf.dense_stencil(4, 4, 4), dtype=torch.float64)
+    A = A0 + torch.diag(torch.nn.functional.softplus(th))
+    xs = torch.linalg.solve(A, torch.tensor(b, dtype=torch.float64))
+    loss = 0.5 * ((xs - torch.tensor(xt, dtype=torch.float64)) ** 2).sum()
+    loss.backward()
+    np.testing.assert_allclose(g, th.grad.numpy(), rtol=1e-9, atol=1e-13)
+
+
+def test_theta_gradient_matches_finite_differences():
+    rng = np.random.default_rng(11)
+    n = 8 * 8 * 8
+    theta = rng.normal(0, 0.5, n)
+    b = rng.uniform(-1, 1, n)
+    xt = rng.uniform(-1, 1, n)
+
+    def loss(th):
+        o = Oracle(8, 8, 8, levels=4, theta=th)
+        x, _, _, st = o.pcg(b, max_iters=300, tol=1e-14)
+        assert st == 0
+        return 0.5 * np.sum((x - xt) ** 2), x
+
+    _, x = loss(theta)
+    o = Oracle(8, 8, 8, levels=4, theta=theta)
+    lam, _, _, _ = o.pcg(x - xt, max_iters=300, tol=1e-14)
+    g = Oracle.theta_grad(lam, x, theta)
+    # central differences with h = 1e-4: truncation O(h^2) and cancellation
+    # eps*|L|/h (|L| ~ 1e2) are both below 1e-9 in absolute terms here
+    h = 1e-4
+    for i in [0, 7, 100, 273, 511]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (loss(tp)[0] - loss(tm)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-9 + 1e-6 * abs(g[i])
