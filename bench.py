@@ -1,0 +1,264 @@
+"""Benchmark: FP64 MG-PCG on the 128^3 27-point problem (50 iterations per step).
+
+One step = one complete 50-iteration MG-PCG solve (4-level V-cycle with the
+8-colour symmetric Gauss-Seidel smoother, injection transfers, CG updates) of
+the 128x128x128 problem with b = A*1, x0 = 0, inputs resident in HBM in the
+library's internal layout.  value = nominal GFLOP/s of the method as written
+(0.810 GFLOP per iteration), i.e. whole-job throughput.
+
+Also reported on the same line:
+  roofline      the dominant kernel (one colour pass of the level-0 sweep),
+                algorithmic bytes per launch / average launch time from HIP
+                events on the stream it runs on, against 8 TB/s;
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample;
+  extensions    FP32-V-cycle vs FP64 to 1e-9 at 192^3, 64 batched uneven
+                grids and 16 right-hand sides vs one-at-a-time solves.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extensions]
+       [--no-cpu-baseline] [--only-kernel]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MG-PCG GFLOP/s + %HBM roofline at 128³ FP64; FP32-MG/batched speedup at 1e-9"
+GRID = (128, 128, 128)
+ITERS = 50
+LEVELS = 4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "library.hip", "kernels.h", "mgpcg_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2304_08232_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(per_launch_alg_bytes):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "pass_l0_128cubed_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_solves(torch, mg, prob, b, x, steps, warmup, iters):
+    for _ in range(warmup):
+        x.zero_()
+        prob.solve_async(b, x, max_iters=iters, layout=mg.INTERNAL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.solve_async(b, x, max_iters=iters, layout=mg.INTERNAL)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def time_to_tol(torch, prob, b, tol, max_iters=1000, reps=3):
+    """Seconds for a solve to rel_tol (natural layout in/out), best of reps."""
+    best, out = None, None
+    for _ in range(reps + 1):  # first is a warmup (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, h, its, st = prob.solve(b, max_iters=max_iters, tol=tol)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        if out is None:
+            out = (x, h, its, st)
+            continue
+        best = t if best is None else min(best, t)
+        out = (x, h, its, st)
+    return best, out
+
+
+def dominant_kernel(torch, mg, prob, reps=20):
+    """Average duration of one level-0 colour pass (k_pass) from HIP events
+    recorded on the stream the library launches on."""
+    n = prob.n(0)
+    r = torch.rand(n, dtype=torch.float64, device="cuda")
+    z = torch.rand(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        mg.mgpcg_gs_sweep(prob.h, 0, r, z, layout=mg.INTERNAL, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        mg.mgpcg_gs_sweep(prob.h, 0, r, z, layout=mg.INTERNAL, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    launches = reps * 16
+    return e0.elapsed_time(e1) * 1e-3 / launches, launches
+
+
+def cpu_baseline(iters=5):
+    from oracle import Oracle
+    from paper_2304_08232_amd import perfmodel
+    o = Oracle(*GRID, levels=LEVELS)
+    b = o.spmv(np.ones(o.n()))
+    t0 = time.perf_counter()
+    x, h, it, st = o.pcg(b, max_iters=iters)
+    t = time.perf_counter() - t0
+    _, F = perfmodel.iteration([GRID], LEVELS, "fp64")
+    return {"value": round(F * iters / t / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} MG-PCG iterations of the 128^3 FP64 problem (setup untimed), "
+                      f"single-threaded C oracle, {t:.1f} s"}
+
+
+def extensions(torch, mg):
+    from paper_2304_08232_amd import inputs, perfmodel
+    ext = {}
+    # FP32 V-cycle inside FP64 CG vs FP64, 192^3, to 1e-9
+    dims = (192, 192, 192)
+    p64 = mg.Problem(dims, levels=LEVELS, mg_dtype="fp64")
+    b = p64.make_rhs_ones() + torch.tensor(inputs.perturbation(3, p64.n()), device="cuda")
+    t64, (x64, h64, it64, st64) = time_to_tol(torch, p64, b, 1e-9)
+    p64.close()
+    p32 = mg.Problem(dims, levels=LEVELS, mg_dtype="fp32")
+    t32, (x32, h32, it32, st32) = time_to_tol(torch, p32, b, 1e-9)
+    p32.close()
+    err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    B64, F64 = perfmodel.iteration([dims], LEVELS, "fp64")
+    B32, _ = perfmodel.iteration([dims], LEVELS, "fp32")
+    ext["fp32_mg_192cubed"] = {
+        "fp64_s": round(t64, 5), "fp32_s": round(t32, 5), "speedup": round(t64 / t32, 3),
+        "fp64_iters": int(it64[0]), "fp32_iters": int(it32[0]),
+        "fp64_relres": float(h64[0][it64[0] - 1]), "fp32_relres": float(h32[0][it32[0] - 1]),
+        "rel_diff_x_fp32_vs_fp64": err,
+        "fp64_hbm_frac": round(B64 * int(it64[0]) / t64 / 8e12, 3),
+        "fp32_hbm_frac_nominal": round(B32 * int(it32[0]) / t32 / 8e12, 3)}
+    del x64, x32, b
+    torch.cuda.empty_cache()
+    log("fp32-mg:", ext["fp32_mg_192cubed"])
+
+    # 64 uneven grids batched vs one at a time
+    dims_list = inputs.batch_dims(4, 64)
+    sizes = [a * b_ * c for a, b_, c in dims_list]
+    bb = torch.tensor(inputs.batch_rhs(44, sizes), device="cuda")
+    pb = mg.Problem(dims_list, levels=LEVELS)
+    tb, (xb, hb, itb, stb) = time_to_tol(torch, pb, bb, 1e-9)
+    pb.close()
+    tsum, its_single = 0.0, []
+    off = 0
+    for d, n in zip(dims_list, sizes):
+        ps = mg.Problem(d, levels=LEVELS)
+        ts, (xs, hs, its_, sts) = time_to_tol(torch, ps, bb[off:off + n].contiguous(), 1e-9, reps=1)
+        tsum += ts
+        its_single.append(int(its_[0]))
+        off += n
+        ps.close()
+    ext["batched_64_grids"] = {
+        "total_rows": int(sum(sizes)), "batched_s": round(tb, 5), "sum_single_s": round(tsum, 5),
+        "speedup": round(tsum / tb, 3), "iters_batched": [int(v) for v in itb],
+        "iters_match_single": bool(list(map(int, itb)) == its_single),
+        "all_converged": bool(stb == mg.OK)}
+    log("batched:", {k: v for k, v in ext["batched_64_grids"].items() if k != "iters_batched"})
+    del bb, xb
+    torch.cuda.empty_cache()
+
+    # 16 right-hand sides on one 128^3 grid vs 16 single solves
+    n = GRID[0] ** 3
+    B = torch.tensor(inputs.multi_rhs(41, 16, n), device="cuda")
+    pm = mg.Problem(GRID, levels=LEVELS, nrhs=16)
+    tm, (xm, hm, itm, stm) = time_to_tol(torch, pm, B, 1e-9)
+    pm.close()
+    ps = mg.Problem(GRID, levels=LEVELS)
+    tsum = 0.0
+    its_single = []
+    for v in range(16):
+        ts, (_, _, its_, _) = time_to_tol(torch, ps, B[v * n:(v + 1) * n].contiguous(), 1e-9, reps=1)
+        tsum += ts
+        its_single.append(int(its_[0]))
+    ps.close()
+    ext["multi_rhs_16_128cubed"] = {
+        "multi_s": round(tm, 5), "sum_single_s": round(tsum, 5), "speedup": round(tsum / tm, 3),
+        "iters": [int(v) for v in itm], "iters_match_single": bool(list(map(int, itm)) == its_single),
+        "all_converged": bool(stm == mg.OK)}
+    log("multi-rhs:", {k: v for k, v in ext["multi_rhs_16_128cubed"].items() if k != "iters"})
+    return ext
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extensions", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-kernel", action="store_true",
+                    help="time only the dominant kernel (for counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is a "
+              "single-GPU build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_08232_amd import mgpcg as mg
+    from paper_2304_08232_amd import perfmodel
+
+    torch.cuda.set_device(0)
+    prob = mg.Problem(GRID, levels=LEVELS)
+    log(f"setup done: n={prob.n(0)} nnz={prob.nnz(0)}")
+    per_launch_bytes = perfmodel.sweep_pass_bytes(GRID)
+    t_launch, launches = dominant_kernel(torch, mg, prob)
+    log(f"dominant kernel: {t_launch * 1e6:.2f} us per colour pass over {launches} launches")
+    if args.only_kernel:
+        return
+
+    b = prob.make_rhs_ones(layout=mg.INTERNAL)
+    x = prob.zeros()
+    t_step = time_to_solve = time_solves(torch, mg, prob, b, x, args.steps, args.warmup, ITERS)
+    hist = np.zeros(ITERS)
+    its = np.zeros(1, np.int32)
+    st = mg.mgpcg_solve_result(prob.h, ITERS, hist, its)
+    log(f"solve: {t_step * 1e3:.3f} ms per 50 iterations, relres[50] = {hist[-1]:.6e}, status {st}")
+    B, F = perfmodel.iteration([GRID], LEVELS, "fp64")
+    gflops = F * ITERS / time_to_solve / 1e9
+    hbm_frac = B * ITERS / time_to_solve / (perfmodel.HBM_PEAK_GBS * 1e9)
+    achieved = per_launch_bytes / t_launch / 1e9
+    line = {
+        "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fp64_mgpcg_128cubed_50it", "grid": list(GRID), "levels": LEVELS,
+                   "iterations_per_step": ITERS, "colour_order": 0, "rhs": "A*ones", "x0": "zeros",
+                   "layout": "internal (resident in HBM)"},
+        "nominal_hbm_frac": round(hbm_frac, 4),
+        "us_per_iteration": round(t_step / ITERS * 1e6, 2),
+        "final_relres": float(hist[-1]),
+        "roofline": {"bound": "hbm", "kernel": "k_pass<double,1,false> (level-0 colour pass)",
+                     "achieved": round(achieved, 1), "peak": perfmodel.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / perfmodel.HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(per_launch_bytes),
+                     "alg_bytes_per_launch": int(per_launch_bytes),
+                     "avg_launch_us": round(t_launch * 1e6, 3)},
+    }
+    if not args.no_extensions:
+        del b, x
+        prob.close()
+        torch.cuda.empty_cache()
+        line["extensions"] = extensions(torch, mg)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * mgpcg.h -- C ABI of the MI355X (gfx950) multigrid-preconditioned conjugate
+ * gradient library for the 27-point HPCG stencil.
+ *
+ * Method: arXiv 2304.08232, "Effective implementation of the High Performance
+ * Conjugate Gradient benchmark on GraphBLAS":
+ *   - problem (27-point operator, b, x0)         Sec. II-A, II-B
+ *   - preconditioned CG                           Sec. II-C
+ *   - multigrid V-cycle                           Sec. II-D, Listing 1
+ *   - Gauss-Seidel update                         Sec. II-E, Eq. (1)
+ *   - coloured symmetric Gauss-Seidel (RBGS)      Sec. III-A, Listings 2-3
+ *   - greedy colouring                            Sec. III-A
+ *   - straight-injection restriction/refinement   Sec. II-F, Sec. III-B
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an mgpcg_status.  Nothing is thrown across the ABI.
+ *   On a negative status, mgpcg_last_error() returns a message (thread-local).
+ * - Argument checks happen before anything is launched; a call that fails them
+ *   has no effect.
+ * - Vector arguments are DEVICE pointers (e.g. torch.Tensor.data_ptr()) owned
+ *   by the caller, which must keep them alive until the stream work is done.
+ *   They hold FP64 values.  Matrices, colour tables, transfer maps and all
+ *   workspaces are owned by the problem handle.
+ * - Streams are HIP streams (NULL = the legacy default stream).  Calls are
+ *   asynchronous on the stream unless stated otherwise.
+ * - A problem holds G >= 1 independent grids ("batched problems") with R >= 1
+ *   right-hand sides each, i.e. S = G*R systems.  Vectors at level l are packed
+ *   grid after grid; within a grid, right-hand side after right-hand side;
+ *   within a right-hand side, one value per grid point.
+ * - Layout MGPCG_LAYOUT_NATURAL: grid point order i = ix + nx*(iy + ny*iz).
+ *   MGPCG_LAYOUT_INTERNAL: the library's own colour-major, rhs-interleaved
+ *   order (for benchmarks that want no permutation in the timed region; use
+ *   mgpcg_to_internal / mgpcg_to_natural to convert).
+ */
+#ifndef MGPCG_H
+#define MGPCG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgpcg_problem mgpcg_problem;
+
+typedef enum {
+    MGPCG_OK = 0,
+    MGPCG_NOT_CONVERGED = 1,       /* tol > 0 and max_iters reached; results valid */
+    MGPCG_ERR_INVALID_ARG = -1,    /* NULL pointer, bad enum, bad level, ... */
+    MGPCG_ERR_DIMS = -2,           /* dims < 1, levels out of range, dims not divisible */
+    MGPCG_ERR_OOM = -3,            /* device allocation failed */
+    MGPCG_ERR_HIP = -4,            /* a HIP runtime call failed (text in last_error) */
+    MGPCG_ERR_BREAKDOWN = -5,      /* <p,Ap> not finite or not positive */
+    MGPCG_ERR_NO_DEVICE = -6       /* no usable GPU */
+} mgpcg_status;
+
+enum { MGPCG_FP64 = 0, MGPCG_FP32 = 1 };
+enum { MGPCG_LAYOUT_NATURAL = 0, MGPCG_LAYOUT_INTERNAL = 1 };
+#define MGPCG_MAX_LEVELS 8
+#define MGPCG_MAX_RHS 16
+
+typedef struct {
+    int ngrids;          /* G >= 1 */
+    const int *dims;     /* HOST array of 3*G ints: nx, ny, nz of each grid */
+    int levels;          /* 1..MGPCG_MAX_LEVELS; every dim divisible by 2^(levels-1) */
+    int nrhs;            /* R in {1, 2, 4, 8, 16} */
+    int mg_dtype;        /* MGPCG_FP64, or MGPCG_FP32 for an FP32 V-cycle inside FP64 CG */
+    int colour_order;    /* 0: greedy colour numbering as found (Sec. III-A);
+                            1: numbering reversed, so colour classes are swept
+                               in the opposite order */
+    const double *theta; /* DEVICE pointer or NULL.  When set: one value per
+                            level-0 grid point (packed over grids, natural
+                            order); the diagonal becomes 26 + softplus(theta_i)
+                            and coarse levels take theta at the injection point */
+} mgpcg_config;
+
+/* Sec. II-A/B, II-D, III-A: build the level hierarchy on the current device:
+ * per level the 27-point operator (diagonal 26, off-diagonals -1 for every
+ * in-grid neighbour), its greedy colouring, and the injection maps.  The
+ * operator is stored as 27-slot ELL with FP64 (and/or FP32) values and int32
+ * column indices, rows grouped by colour.  Synchronises the stream before
+ * returning.  *out receives the handle (NULL on failure). */
+mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_problem **out);
+
+/* Releases every device buffer of the handle.  NULL is accepted. */
+mgpcg_status mgpcg_destroy(mgpcg_problem *p);
+
+/* Sizes at one level, summed over grids: rows n, structural nonzeros nnz
+ * (closed form (3nx-2)(3ny-2)(3nz-2) per grid), and ELL slots (27 per row). */
+mgpcg_status mgpcg_info(const mgpcg_problem *p, int level, int64_t *n, int64_t *nnz,
+                        int64_t *ell_slots);
+
+/* Replaces the coefficient field: theta as in mgpcg_config (DEVICE, level-0
+ * points).  Rewrites the diagonal on every level. */
+mgpcg_status mgpcg_set_theta(mgpcg_problem *p, const double *theta, hipStream_t stream);
+
+/* Permutes an FP64 vector of level `level` (all grids, all rhs) between the
+ * natural and the internal layout.  src and dst must not overlap. */
+mgpcg_status mgpcg_to_internal(const mgpcg_problem *p, int level, const double *src, double *dst,
+                               hipStream_t stream);
+mgpcg_status mgpcg_to_natural(const mgpcg_problem *p, int level, const double *src, double *dst,
+                              hipStream_t stream);
+
+/* Sec. II-C: y = A_l x at level `level`.  Level 0 uses the FP64 operator; a
+ * coarser level uses the V-cycle precision (FP32 problems round x to FP32 and
+ * widen y back).  x and y must not overlap. */
+mgpcg_status mgpcg_spmv(const mgpcg_problem *p, int level, const double *x, double *y, int layout,
+                        hipStream_t stream);
+
+/* b = A_0 * 1 (so that the exact solution is all ones).  FP64. */
+mgpcg_status mgpcg_make_rhs_ones(const mgpcg_problem *p, double *b, int layout, hipStream_t stream);
+
+/* Sec. III-A, Listings 2-3 (forward pass) and Sec. II-E (symmetric form):
+ * one symmetric coloured Gauss-Seidel sweep at `level`, in place on z:
+ * colours 0..c-1, then c-1..0; for each row i of the colour being swept
+ * z_i <- (r_i - sum_j a_ij z_j + z_i a_ii) / a_ii with the sum over the whole
+ * row.  Runs in the V-cycle precision.  r and z must not overlap. */
+mgpcg_status mgpcg_gs_sweep(const mgpcg_problem *p, int level, const double *r, double *z, int layout,
+                            hipStream_t stream);
+
+/* Sec. II-D Listing 1 and Sec. II-F: rc = inject(r - A_l z), the residual at
+ * the injection points (2jx, 2jy, 2jz) of level `level` written to level+1.
+ * V-cycle precision.  Requires level+1 < levels. */
+mgpcg_status mgpcg_restrict(const mgpcg_problem *p, int level, const double *r, const double *z,
+                            double *rc, int layout, hipStream_t stream);
+
+/* Sec. II-F, Listing 1: z += refine(zc), i.e. zc added at the injection
+ * points of level `level`.  V-cycle precision. */
+mgpcg_status mgpcg_prolong_add(const mgpcg_problem *p, int level, const double *zc, double *z,
+                               int layout, hipStream_t stream);
+
+/* Sec. II-D, Listing 1: z = M^{-1} r, one V-cycle from z = 0: symmetric sweep,
+ * restriction, recursion, refinement, symmetric sweep; the coarsest level does
+ * one symmetric sweep.  r and z are level-0 vectors. */
+mgpcg_status mgpcg_mg_vcycle(const mgpcg_problem *p, const double *r, double *z, int layout,
+                             hipStream_t stream);
+
+/* Sec. II-C: preconditioned CG for all S systems at once, starting from x
+ * (x holds x0 on entry and the iterate on exit).  Per system: r = b - A x,
+ * then per iteration z = M r, rho = <r,z>, p = z + (rho/rho_old) p (p = z at
+ * the first), q = A p, alpha = rho/<p,q>, x += alpha p, r -= alpha q, and the
+ * relative residual ||r||/||r_0|| is recorded.  rel_tol > 0 stops a system at
+ * the first iteration whose relative residual is <= rel_tol; rel_tol = 0 runs
+ * exactly max_iters iterations.  A system whose b - A x0 is zero does 0
+ * iterations.
+ *
+ * history_host: NULL or S*max_iters doubles (system-major); entries past a
+ * system's iteration count are set to 0.  iters_host: NULL or S ints.
+ * When both are NULL and rel_tol == 0 the call is asynchronous (only argument
+ * errors are reported; fetch results with mgpcg_solve_result).  Otherwise it
+ * synchronises the stream and returns MGPCG_OK, MGPCG_NOT_CONVERGED (some
+ * system missed rel_tol) or MGPCG_ERR_BREAKDOWN (some system stopped on a
+ * breakdown; its x is the last good iterate). */
+mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int max_iters,
+                             double rel_tol, double *history_host, int *iters_host, int layout,
+                             hipStream_t stream);
+
+/* Results of the most recent mgpcg_pcg_solve (synchronises the stream).
+ * Same meaning of history_host / iters_host / the returned status as above;
+ * max_iters must equal the value that solve used. */
+mgpcg_status mgpcg_solve_result(mgpcg_problem *p, int max_iters, double *history_host,
+                                int *iters_host, hipStream_t stream);
+
+/* Differentiable solve: with x = A(theta)^{-1} b and the adjoint
+ * lambda = A^{-1} dL/dx (A is symmetric), writes
+ * grad_i = -lambda_i * x_i * logistic(theta_i), the gradient of L with respect
+ * to theta when a_ii = 26 + softplus(theta_i).  Element-wise over the n level-0
+ * points of every grid (R must be 1); any common layout. */
+mgpcg_status mgpcg_theta_grad(const mgpcg_problem *p, const double *lambda, const double *x,
+                              const double *theta, double *grad, hipStream_t stream);
+
+/* Execution mode of mgpcg_pcg_solve: on = 1 (default) captures one CG
+ * iteration into a HIP graph on first use and replays it; on = 0 launches the
+ * iteration's kernels one by one.  Results are identical either way. */
+mgpcg_status mgpcg_set_graph_mode(mgpcg_problem *p, int on);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char *mgpcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGPCG_H */

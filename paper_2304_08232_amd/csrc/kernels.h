@@ -1,0 +1,45 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include "mgpcg_internal.h"
+
+namespace mg {
+
+// Problem setup: fill the ELL operator of one level (values, columns).
+hipError_t launch_build_ell(const mgpcg_problem *P, int level, const double *theta, hipStream_t s);
+
+// natural <-> internal permutation of an FP64 level vector (R rhs)
+hipError_t launch_permute(const mgpcg_problem *P, int level, const double *src, double *dst,
+                          bool to_internal, hipStream_t s);
+
+template <typename T>
+hipError_t launch_spmv(const mgpcg_problem *P, int level, const T *val, const T *x, T *y, hipStream_t s);
+
+// one colour pass of the coloured Gauss-Seidel smoother
+template <typename T>
+hipError_t launch_pass(const mgpcg_problem *P, int level, int k, bool zero_start, const T *val,
+                       const T *r, T *z, const int *done, hipStream_t s);
+
+template <typename T>
+hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, const T *r, const T *z,
+                           T *rc, hipStream_t s);
+
+template <typename T>
+hipError_t launch_prolong(const mgpcg_problem *P, int level, const T *zc, T *z, hipStream_t s);
+
+hipError_t launch_cast_d2f(const double *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_cast_f2d(const float *src, double *dst, int64_t n, hipStream_t s);
+hipError_t launch_fill_d(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_i(int *p, int64_t n, int v, hipStream_t s);
+hipError_t launch_fill_u(unsigned *p, int64_t n, unsigned v, hipStream_t s);
+
+// CG kernels on level 0 (FP64, internal layout), with per-system scalars
+hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s);
+hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s);
+hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s);
+hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s);
+hipError_t launch_update_xr(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s);
+
+hipError_t launch_theta_grad(const double *lam, const double *x, const double *theta, double *grad,
+                             int64_t n, hipStream_t s);
+
+}  // namespace mg

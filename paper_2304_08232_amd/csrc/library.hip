@@ -1,0 +1,873 @@
+// Host side of the MG-PCG library: hierarchy setup, V-cycle and PCG drivers,
+// iteration graph capture, and the C ABI declared in mgpcg.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace mg;
+
+namespace {
+
+thread_local std::string g_err;
+
+mgpcg_status fail(mgpcg_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+mgpcg_status hip_fail(hipError_t e, const char *where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return MGPCG_ERR_HIP;
+}
+
+#define HIP_TRY(expr)                                              \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);          \
+    } while (0)
+
+template <typename T>
+mgpcg_status dalloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) return MGPCG_OK;
+    hipError_t e = hipMalloc((void **)p, (size_t)count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(MGPCG_ERR_OOM, std::string("hipMalloc of ") + std::to_string((size_t)count * sizeof(T)) +
+                                       " bytes failed: " + hipGetErrorString(e));
+    }
+    return MGPCG_OK;
+}
+
+#define ST_TRY(expr)                         \
+    do {                                     \
+        mgpcg_status s_ = (expr);            \
+        if (s_ != MGPCG_OK) return s_;       \
+    } while (0)
+
+template <typename T>
+mgpcg_status upload(T **dst, const std::vector<T> &src, hipStream_t s) {
+    ST_TRY(dalloc(dst, (int64_t)src.size()));
+    if (!src.empty()) {
+        HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // src is pageable and about to go away
+    }
+    return MGPCG_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+// --------------------------------------------------------------- colouring
+//
+// Greedy first-fit colouring in ascending row order (Sec. III-A of the paper)
+// on the 27-point grid produces the parity code (ix&1) + 2(iy&1) + 4(iz&1)
+// over the dimensions of extent >= 2 (bits of extent-1 dimensions are always
+// 0 and are dropped from the numbering).  colour_order 1 reverses the
+// numbering.  These helpers map parity bits <-> colour numbers for one grid.
+
+struct Colouring {
+    int nbits = 0;
+    int bitpos[3] = {-1, -1, -1};  // position of the x/y/z parity bit in the colour number
+    int ncol = 1;
+    int order = 0;
+    Colouring(int nx, int ny, int nz, int ord) {
+        int d[3] = {nx, ny, nz};
+        for (int a = 0; a < 3; ++a)
+            if (d[a] >= 2) bitpos[a] = nbits++;
+        ncol = 1 << nbits;
+        order = ord;
+    }
+    int colour(int bx, int by, int bz) const {
+        int b[3] = {bx, by, bz}, c = 0;
+        for (int a = 0; a < 3; ++a)
+            if (bitpos[a] >= 0) c |= b[a] << bitpos[a];
+        return order ? ncol - 1 - c : c;
+    }
+    void parity(int k, int *b) const {
+        int c = order ? ncol - 1 - k : k;
+        for (int a = 0; a < 3; ++a) b[a] = bitpos[a] >= 0 ? (c >> bitpos[a]) & 1 : 0;
+    }
+};
+
+// points of a dimension of extent `ext` whose coordinate has parity `bit`
+inline int64_t half_count(int ext, int bit) { return ext >= 2 ? (ext + 1 - bit) / 2 : (bit ? 0 : 1); }
+
+mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t s) {
+    const int G = P->G, R = P->R, L = P->L;
+    P->lev.resize(L);
+    P->d_natoff.assign(L, nullptr);
+    std::vector<int> dims0 = P->dims0;
+    ST_TRY(upload(&P->d_dims0, dims0, s));
+
+    for (int l = 0; l < L; ++l) {
+        Level &Lv = P->lev[l];
+        Lv.grids.resize(G);
+        int64_t nat = 0;
+        Lv.ncol = 0;
+        for (int g = 0; g < G; ++g) {
+            LevelGrid &lg = Lv.grids[g];
+            lg.nx = dims0[3 * g] >> l;
+            lg.ny = dims0[3 * g + 1] >> l;
+            lg.nz = dims0[3 * g + 2] >> l;
+            Colouring C(lg.nx, lg.ny, lg.nz, P->colour_order);
+            lg.ncol = C.ncol;
+            lg.nat_off = nat;
+            nat += (int64_t)lg.nx * lg.ny * lg.nz;
+            Lv.nnz += (int64_t)(3 * lg.nx - 2) * (3 * lg.ny - 2) * (3 * lg.nz - 2);
+            Lv.ncol = std::max(Lv.ncol, C.ncol);
+            for (int k = 0; k < 8; ++k) {
+                lg.seg_len[k] = 0;
+                if (k < C.ncol) {
+                    int b[3];
+                    C.parity(k, b);
+                    lg.seg_len[k] = half_count(lg.nx, b[0]) * half_count(lg.ny, b[1]) * half_count(lg.nz, b[2]);
+                }
+            }
+            lg.inj_colour = C.colour(0, 0, 0);
+        }
+        Lv.n = nat;
+        // colour-major across grids
+        Lv.coff.assign(Lv.ncol + 1, 0);
+        int64_t off = 0;
+        for (int k = 0; k < Lv.ncol; ++k) {
+            Lv.coff[k] = off;
+            for (int g = 0; g < G; ++g) {
+                Lv.grids[g].seg_off[k] = off;
+                off += Lv.grids[g].seg_len[k];
+            }
+        }
+        Lv.coff[Lv.ncol] = off;
+        if (off != Lv.n) return fail(MGPCG_ERR_DIMS, "internal: colour classes do not cover the grid");
+        if (Lv.n * kW >= ((int64_t)1 << 31) || Lv.n * R >= ((int64_t)1 << 31))
+            return fail(MGPCG_ERR_DIMS, "problem too large for 32-bit row indices");
+
+        // permutation natural packed -> internal
+        std::vector<int32_t> perm(Lv.n), iperm(Lv.n);
+        std::vector<int64_t> natoff(G + 1);
+        for (int g = 0; g < G; ++g) {
+            const LevelGrid &lg = Lv.grids[g];
+            natoff[g] = lg.nat_off;
+            Colouring C(lg.nx, lg.ny, lg.nz, P->colour_order);
+            for (int iz = 0; iz < lg.nz; ++iz)
+                for (int iy = 0; iy < lg.ny; ++iy)
+                    for (int ix = 0; ix < lg.nx; ++ix) {
+                        int bx = ix & 1, by = iy & 1, bz = iz & 1;
+                        int k = C.colour(bx, by, bz);
+                        int64_t hx = half_count(lg.nx, bx), hy = half_count(lg.ny, by);
+                        int64_t j = (ix >> 1) + hx * ((iy >> 1) + hy * (iz >> 1));
+                        int64_t q = lg.nat_off + ix + (int64_t)lg.nx * (iy + (int64_t)lg.ny * iz);
+                        int64_t in = lg.seg_off[k] + j;
+                        perm[q] = (int32_t)in;
+                        iperm[in] = (int32_t)q;
+                    }
+        }
+        natoff[G] = Lv.n;
+        ST_TRY(upload(&Lv.perm, perm, s));
+        ST_TRY(upload(&Lv.iperm, iperm, s));
+        ST_TRY(upload(&P->d_natoff[l], natoff, s));
+        if (l == 0) ST_TRY(upload(&P->d_natoff0, natoff, s));
+
+        // colour-pass tables: one workgroup per kBlock/R rows, grid-homogeneous
+        std::vector<Seg> tab;
+        Lv.pass_first.assign(Lv.ncol + 1, 0);
+        const int rows_per_block = kBlock / R;
+        for (int k = 0; k < Lv.ncol; ++k) {
+            Lv.pass_first[k] = (int)tab.size();
+            for (int g = 0; g < G; ++g) {
+                const LevelGrid &lg = Lv.grids[g];
+                for (int64_t a = 0; a < lg.seg_len[k]; a += rows_per_block) {
+                    Seg e;
+                    e.row0 = lg.seg_off[k] + a;
+                    e.count = (int32_t)std::min<int64_t>(rows_per_block, lg.seg_len[k] - a);
+                    e.grid = g;
+                    tab.push_back(e);
+                }
+            }
+        }
+        Lv.pass_first[Lv.ncol] = (int)tab.size();
+        ST_TRY(upload(&Lv.pass_tab, tab, s));
+
+        // zero-start forward pass: a colour-k row must skip every slot whose
+        // real neighbour has colour >= k (not written yet in this sweep), and
+        // may skip padding slots.  One mask per colour serves all grids, so
+        // it is the intersection of what each grid allows; if some grid needs
+        // a slot skipped that another grid must read, the level falls back to
+        // clearing z and a general first pass.
+        Lv.zs_ok = true;
+        for (int k = 0; k < 8; ++k) {
+            uint32_t allowed = ~0u, needed = 0;
+            for (int g = 0; g < G; ++g) {
+                const LevelGrid &lg = Lv.grids[g];
+                if (k >= lg.ncol || lg.seg_len[k] == 0) continue;
+                Colouring C(lg.nx, lg.ny, lg.nz, P->colour_order);
+                int b[3];
+                C.parity(k, b);
+                int ext[3] = {lg.nx, lg.ny, lg.nz};
+                for (int sl = 0; sl < kW; ++sl) {
+                    int d[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
+                    bool padding = false;
+                    for (int a = 0; a < 3; ++a)
+                        if (d[a] != 0 && ext[a] < 2) padding = true;
+                    if (padding) continue;
+                    int nb = C.colour(b[0] ^ (d[0] & 1), b[1] ^ (d[1] & 1), b[2] ^ (d[2] & 1));
+                    if (nb >= k) needed |= 1u << sl;
+                    else allowed &= ~(1u << sl);
+                }
+            }
+            Lv.zi_skip[k] = allowed & ((1u << kW) - 1);
+            if ((needed & ~allowed) != 0) Lv.zs_ok = false;
+        }
+        if (G > 1) {
+            std::vector<int32_t> gon(Lv.n);
+            for (int g = 0; g < G; ++g)
+                for (int64_t q = natoff[g]; q < natoff[g + 1]; ++q) gon[q] = g;
+            ST_TRY(upload(&Lv.grid_of_nat, gon, s));
+        }
+    }
+
+    // injection maps (fine level l -> coarse level l+1), sorted by fine row
+    for (int l = 0; l + 1 < L; ++l) {
+        Level &F = P->lev[l];
+        Level &Cc = P->lev[l + 1];
+        std::vector<int32_t> hperm_f(F.n), hperm_c(Cc.n);
+        HIP_TRY(hipMemcpyAsync(hperm_f.data(), F.perm, F.n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hperm_c.data(), Cc.perm, Cc.n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<std::pair<int32_t, int32_t>> pairs;
+        pairs.reserve(Cc.n);
+        for (int g = 0; g < G; ++g) {
+            const LevelGrid &fg = F.grids[g], &cg = Cc.grids[g];
+            for (int jz = 0; jz < cg.nz; ++jz)
+                for (int jy = 0; jy < cg.ny; ++jy)
+                    for (int jx = 0; jx < cg.nx; ++jx) {
+                        int64_t qc = cg.nat_off + jx + (int64_t)cg.nx * (jy + (int64_t)cg.ny * jz);
+                        int64_t qf = fg.nat_off + 2 * jx + (int64_t)fg.nx * (2 * jy + (int64_t)fg.ny * 2 * jz);
+                        pairs.emplace_back(hperm_f[qf], hperm_c[qc]);
+                    }
+        }
+        std::sort(pairs.begin(), pairs.end());
+        std::vector<int32_t> fi(pairs.size()), ci(pairs.size());
+        for (size_t t = 0; t < pairs.size(); ++t) {
+            fi[t] = pairs[t].first;
+            ci[t] = pairs[t].second;
+        }
+        F.n_inj = (int64_t)pairs.size();
+        ST_TRY(upload(&F.inj_fine, fi, s));
+        ST_TRY(upload(&F.inj_coarse, ci, s));
+    }
+
+    // operators, workspaces
+    const bool fp32 = P->mg_dtype == MGPCG_FP32;
+    for (int l = 0; l < L; ++l) {
+        Level &Lv = P->lev[l];
+        if (l == 0 || !fp32) ST_TRY(dalloc(&Lv.val64, Lv.n * kW));
+        if (fp32) ST_TRY(dalloc(&Lv.val32, Lv.n * kW));
+        ST_TRY(dalloc(&Lv.col, Lv.n * kW));
+        if (fp32) {
+            float *r32, *z32;
+            ST_TRY(dalloc(&r32, Lv.n * R));
+            ST_TRY(dalloc(&z32, Lv.n * R));
+            Lv.r = r32;
+            Lv.z = z32;
+        } else if (l > 0) {
+            double *r64, *z64;
+            ST_TRY(dalloc(&r64, Lv.n * R));
+            ST_TRY(dalloc(&z64, Lv.n * R));
+            Lv.r = r64;
+            Lv.z = z64;
+        }
+        HIP_TRY(launch_build_ell(P, l, theta, s));
+    }
+
+    // level-0 reduction table: grid by grid, chunks of kRedElems/R rows
+    {
+        const Level &L0 = P->lev[0];
+        std::vector<Seg> tab;
+        std::vector<int> gb(G + 1, 0);
+        const int rows = kRedElems / R;
+        for (int g = 0; g < G; ++g) {
+            gb[g] = (int)tab.size();
+            const LevelGrid &lg = L0.grids[g];
+            for (int k = 0; k < L0.ncol; ++k)
+                for (int64_t a = 0; a < lg.seg_len[k]; a += rows) {
+                    Seg e;
+                    e.row0 = lg.seg_off[k] + a;
+                    e.count = (int32_t)std::min<int64_t>(rows, lg.seg_len[k] - a);
+                    e.grid = g;
+                    tab.push_back(e);
+                }
+        }
+        gb[G] = (int)tab.size();
+        P->n_red = (int)tab.size();
+        P->red_gb_host = gb;
+        ST_TRY(upload(&P->red_tab, tab, s));
+        ST_TRY(upload(&P->red_gb, gb, s));
+        const int64_t n0 = L0.n * R;
+        ST_TRY(dalloc(&P->x, n0));
+        ST_TRY(dalloc(&P->r, n0));
+        ST_TRY(dalloc(&P->z, n0));
+        ST_TRY(dalloc(&P->p, n0));
+        ST_TRY(dalloc(&P->q, n0));
+        ST_TRY(dalloc(&P->b, n0));
+        const int S = P->S;
+        Scalars &sc = P->sc;
+        ST_TRY(dalloc(&sc.rho, S));
+        ST_TRY(dalloc(&sc.rho_old, S));
+        ST_TRY(dalloc(&sc.alpha, S));
+        ST_TRY(dalloc(&sc.beta, S));
+        ST_TRY(dalloc(&sc.nr0, S));
+        ST_TRY(dalloc(&sc.pq, S));
+        ST_TRY(dalloc(&sc.iter, S));
+        ST_TRY(dalloc(&sc.done, S));
+        ST_TRY(dalloc(&sc.status, S));
+        ST_TRY(dalloc(&sc.ndone, 1));
+        ST_TRY(dalloc(&sc.tickets, (int64_t)kTicketKinds * G));
+        ST_TRY(dalloc(&sc.partials, (int64_t)P->n_red * R));
+        HIP_TRY(launch_fill_u(sc.tickets, (int64_t)kTicketKinds * G, 0u, s));
+    }
+    HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    return MGPCG_OK;
+}
+
+void free_problem(mgpcg_problem *P) {
+    if (!P) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(P->device);
+    (void)hipDeviceSynchronize();
+    for (auto &Lv : P->lev) {
+        dfree(Lv.val64); dfree(Lv.val32); dfree(Lv.col); dfree(Lv.perm); dfree(Lv.iperm);
+        dfree(Lv.grid_of_nat); dfree(Lv.pass_tab); dfree(Lv.inj_fine); dfree(Lv.inj_coarse);
+        dfree(Lv.r); dfree(Lv.z); dfree(Lv.t0); dfree(Lv.t1); dfree(Lv.t2);
+    }
+    for (auto &p : P->d_natoff) dfree(p);
+    dfree(P->d_dims0); dfree(P->d_natoff0); dfree(P->red_tab); dfree(P->red_gb);
+    dfree(P->x); dfree(P->r); dfree(P->z); dfree(P->p); dfree(P->q); dfree(P->b);
+    Scalars &sc = P->sc;
+    dfree(sc.rho); dfree(sc.rho_old); dfree(sc.alpha); dfree(sc.beta); dfree(sc.nr0); dfree(sc.pq);
+    dfree(sc.iter); dfree(sc.done); dfree(sc.status); dfree(sc.ndone); dfree(sc.tickets);
+    dfree(sc.partials);
+    dfree(P->hist);
+    if (P->pinned_ndone) (void)hipHostFree(P->pinned_ndone);
+    if (P->iter_graph) (void)hipGraphExecDestroy(P->iter_graph);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    (void)hipSetDevice(cur);
+    delete P;
+}
+
+// ----------------------------------------------------------------- drivers
+
+// one symmetric sweep: colours 0..c-1 then c-1..0
+template <typename T>
+hipError_t sweep(const mgpcg_problem *P, int l, const T *val, const T *r, T *z, bool zero_start,
+                 const int *done, hipStream_t s) {
+    const Level &Lv = P->lev[l];
+    hipError_t e;
+    for (int k = 0; k < Lv.ncol; ++k)
+        if ((e = launch_pass<T>(P, l, k, zero_start, val, r, z, done, s)) != hipSuccess) return e;
+    for (int k = Lv.ncol - 1; k >= 0; --k)
+        if ((e = launch_pass<T>(P, l, k, false, val, r, z, done, s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template <typename T>
+const T *level_val(const mgpcg_problem *P, int l);
+template <>
+const double *level_val<double>(const mgpcg_problem *P, int l) { return P->lev[l].val64; }
+template <>
+const float *level_val<float>(const mgpcg_problem *P, int l) { return P->lev[l].val32; }
+
+// Listing 1: z0 = MG(0, r0); every level starts from z = 0.
+template <typename T>
+hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, hipStream_t s) {
+    const int L = P->L;
+    auto rl = [&](int l) -> const T * { return l == 0 ? r0 : (const T *)P->lev[l].r; };
+    auto zl = [&](int l) -> T * { return l == 0 ? z0 : (T *)P->lev[l].z; };
+    hipError_t e;
+    for (int l = 0; l < L; ++l) {
+        const bool zs = P->lev[l].zs_ok;
+        if (!zs) {
+            hipError_t fe = sizeof(T) == 8 ? launch_fill_d((double *)zl(l), P->lev[l].n * P->R, 0.0, s)
+                                           : launch_fill_u((unsigned *)zl(l), P->lev[l].n * P->R, 0u, s);
+            if (fe != hipSuccess) return fe;
+        }
+        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), zs, done, s)) != hipSuccess) return e;
+        if (l + 1 < L &&
+            (e = launch_restrict<T>(P, l, level_val<T>(P, l), rl(l), zl(l), (T *)P->lev[l + 1].r, s)) !=
+                hipSuccess)
+            return e;
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        if ((e = launch_prolong<T>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
+        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), false, done, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// z = M^{-1} r on the CG vectors (FP64, internal layout)
+hipError_t precondition(const mgpcg_problem *P, const double *r, double *z, const int *done, hipStream_t s) {
+    if (P->mg_dtype == MGPCG_FP64) return vcycle<double>(P, r, z, done, s);
+    const Level &L0 = P->lev[0];
+    hipError_t e;
+    const int64_t n = L0.n * P->R;
+    if ((e = launch_cast_d2f(r, (float *)L0.r, n, s)) != hipSuccess) return e;
+    if ((e = vcycle<float>(P, (const float *)L0.r, (float *)L0.z, done, s)) != hipSuccess) return e;
+    return launch_cast_f2d((const float *)L0.z, z, n, s);
+}
+
+hipError_t cg_iteration(mgpcg_problem *P, double tol, hipStream_t s) {
+    hipError_t e;
+    if ((e = precondition(P, P->r, P->z, P->sc.done, s)) != hipSuccess) return e;
+    if ((e = launch_dot_rz(P, s)) != hipSuccess) return e;
+    if ((e = launch_update_p(P, s)) != hipSuccess) return e;
+    if ((e = launch_spmv_pq(P, s)) != hipSuccess) return e;
+    return launch_update_xr(P, tol, P->hist_cap, s);
+}
+
+// ------------------------------------------------------- argument helpers
+
+mgpcg_status check_problem(const mgpcg_problem *P) {
+    if (!P) return fail(MGPCG_ERR_INVALID_ARG, "problem handle is NULL");
+    return MGPCG_OK;
+}
+mgpcg_status check_level(const mgpcg_problem *P, int level, bool need_coarser = false) {
+    ST_TRY(check_problem(P));
+    if (level < 0 || level >= P->L || (need_coarser && level + 1 >= P->L))
+        return fail(MGPCG_ERR_INVALID_ARG, "level " + std::to_string(level) + " out of range");
+    return MGPCG_OK;
+}
+mgpcg_status check_layout(int layout) {
+    if (layout != MGPCG_LAYOUT_NATURAL && layout != MGPCG_LAYOUT_INTERNAL)
+        return fail(MGPCG_ERR_INVALID_ARG, "layout must be MGPCG_LAYOUT_NATURAL or MGPCG_LAYOUT_INTERNAL");
+    return MGPCG_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+mgpcg_status ensure_scratch(mgpcg_problem *P, int l) {
+    Level &Lv = P->lev[l];
+    if (!Lv.t0) {
+        ST_TRY(dalloc(&Lv.t0, Lv.n * P->R));
+        ST_TRY(dalloc(&Lv.t1, Lv.n * P->R));
+        ST_TRY(dalloc(&Lv.t2, Lv.n * P->R));
+    }
+    return MGPCG_OK;
+}
+
+// bring an FP64 level vector into internal layout (copy into dst when natural)
+mgpcg_status in_vec(const mgpcg_problem *P, int l, const double *src, double *dst, int layout, hipStream_t s) {
+    if (layout == MGPCG_LAYOUT_NATURAL) HIP_TRY(launch_permute(P, l, src, dst, true, s));
+    else HIP_TRY(hipMemcpyAsync(dst, src, P->lev[l].n * P->R * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return MGPCG_OK;
+}
+mgpcg_status out_vec(const mgpcg_problem *P, int l, const double *src, double *dst, int layout, hipStream_t s) {
+    if (layout == MGPCG_LAYOUT_NATURAL) HIP_TRY(launch_permute(P, l, src, dst, false, s));
+    else HIP_TRY(hipMemcpyAsync(dst, src, P->lev[l].n * P->R * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return MGPCG_OK;
+}
+
+mgpcg_status fetch_result(mgpcg_problem *P, int max_iters, double *history_host, int *iters_host,
+                          hipStream_t s) {
+    const int S = P->S;
+    std::vector<int> iters(S), status(S);
+    HIP_TRY(hipMemcpyAsync(iters.data(), P->sc.iter, S * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(status.data(), P->sc.status, S * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (history_host && max_iters > 0) {
+        if (max_iters > P->hist_cap) return fail(MGPCG_ERR_INVALID_ARG, "max_iters exceeds the last solve's");
+        HIP_TRY(hipMemcpy2DAsync(history_host, (size_t)max_iters * sizeof(double), P->hist,
+                                 (size_t)P->hist_cap * sizeof(double), (size_t)max_iters * sizeof(double),
+                                 S, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (iters_host) memcpy(iters_host, iters.data(), S * sizeof(int));
+    bool breakdown = false, unconverged = false;
+    for (int i = 0; i < S; ++i) {
+        if (status[i] == MGPCG_ERR_BREAKDOWN) breakdown = true;
+        else if (status[i] != 1 && P->last_tol > 0.0) unconverged = true;
+    }
+    if (breakdown) return fail(MGPCG_ERR_BREAKDOWN, "<p,Ap> was not finite or not positive for some system");
+    return unconverged ? MGPCG_NOT_CONVERGED : MGPCG_OK;
+}
+
+// Runs `body(r_internal_T, z_internal_T)` at level l in the V-cycle precision
+// with FP64 caller vectors r (read) and z (read/write), any layout.
+template <typename F>
+mgpcg_status with_level_vectors(mgpcg_problem *p, int l, const double *r, double *z, int layout,
+                                       hipStream_t s, bool read_z, F body) {
+    ST_TRY(ensure_scratch(p, l));
+    Level &Lv = p->lev[l];
+    const int64_t n = Lv.n * p->R;
+    const double *ri = r;
+    double *zi = z;
+    if (layout == MGPCG_LAYOUT_NATURAL) {
+        HIP_TRY(launch_permute(p, l, r, Lv.t0, true, s));
+        if (read_z) HIP_TRY(launch_permute(p, l, z, Lv.t1, true, s));
+        ri = Lv.t0;
+        zi = Lv.t1;
+    }
+    if (p->mg_dtype == MGPCG_FP64) {
+        HIP_TRY(body((const void *)ri, (void *)zi));
+    } else {
+        HIP_TRY(launch_cast_d2f(ri, (float *)Lv.r, n, s));
+        if (read_z) HIP_TRY(launch_cast_d2f(zi, (float *)Lv.z, n, s));
+        HIP_TRY(body((const void *)Lv.r, Lv.z));
+        HIP_TRY(launch_cast_f2d((const float *)Lv.z, zi, n, s));
+    }
+    if (layout == MGPCG_LAYOUT_NATURAL) HIP_TRY(launch_permute(p, l, zi, z, false, s));
+    return MGPCG_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char *mgpcg_last_error(void) { return g_err.c_str(); }
+
+mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_problem **out) {
+    if (!out) return fail(MGPCG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg || !cfg->dims) return fail(MGPCG_ERR_INVALID_ARG, "config or dims is NULL");
+    if (cfg->ngrids < 1) return fail(MGPCG_ERR_DIMS, "ngrids must be >= 1");
+    if (cfg->levels < 1 || cfg->levels > MGPCG_MAX_LEVELS)
+        return fail(MGPCG_ERR_DIMS, "levels must be in 1.." + std::to_string(MGPCG_MAX_LEVELS));
+    const int R = cfg->nrhs;
+    if (R != 1 && R != 2 && R != 4 && R != 8 && R != 16)
+        return fail(MGPCG_ERR_INVALID_ARG, "nrhs must be 1, 2, 4, 8 or 16");
+    if (cfg->mg_dtype != MGPCG_FP64 && cfg->mg_dtype != MGPCG_FP32)
+        return fail(MGPCG_ERR_INVALID_ARG, "mg_dtype must be MGPCG_FP64 or MGPCG_FP32");
+    if (cfg->colour_order != 0 && cfg->colour_order != 1)
+        return fail(MGPCG_ERR_INVALID_ARG, "colour_order must be 0 or 1");
+    const int div = 1 << (cfg->levels - 1);
+    int64_t total = 0;
+    for (int g = 0; g < cfg->ngrids; ++g) {
+        for (int a = 0; a < 3; ++a) {
+            int d = cfg->dims[3 * g + a];
+            if (d < 1) return fail(MGPCG_ERR_DIMS, "grid dimensions must be >= 1");
+            if (d % div)
+                return fail(MGPCG_ERR_DIMS, "grid " + std::to_string(g) + ": dimension " + std::to_string(d) +
+                                                " not divisible by 2^(levels-1) = " + std::to_string(div));
+        }
+        total += (int64_t)cfg->dims[3 * g] * cfg->dims[3 * g + 1] * cfg->dims[3 * g + 2];
+        if (total > ((int64_t)1 << 31) / kW) return fail(MGPCG_ERR_DIMS, "problem too large");
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(MGPCG_ERR_NO_DEVICE, "no HIP device available");
+    }
+    mgpcg_problem *P = new (std::nothrow) mgpcg_problem();
+    if (!P) return fail(MGPCG_ERR_OOM, "host allocation failed");
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return fail(MGPCG_ERR_NO_DEVICE, "hipGetDevice failed");
+    }
+    P->G = cfg->ngrids;
+    P->R = R;
+    P->S = P->G * R;
+    P->L = cfg->levels;
+    P->mg_dtype = cfg->mg_dtype;
+    P->colour_order = cfg->colour_order;
+    P->dims0.assign(cfg->dims, cfg->dims + 3 * cfg->ngrids);
+    mgpcg_status st = build_hierarchy(P, cfg->theta, stream);
+    if (st != MGPCG_OK) {
+        std::string msg = g_err;
+        free_problem(P);
+        g_err = msg;
+        return st;
+    }
+    *out = P;
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_destroy(mgpcg_problem *p) {
+    free_problem(p);
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_info(const mgpcg_problem *p, int level, int64_t *n, int64_t *nnz, int64_t *ell_slots) {
+    ST_TRY(check_level(p, level));
+    const Level &Lv = p->lev[level];
+    if (n) *n = Lv.n;
+    if (nnz) *nnz = Lv.nnz;
+    if (ell_slots) *ell_slots = Lv.n * kW;
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_set_theta(mgpcg_problem *p, const double *theta, hipStream_t stream) {
+    ST_TRY(check_problem(p));
+    DeviceGuard dg(p->device);
+    for (int l = 0; l < p->L; ++l) HIP_TRY(launch_build_ell(p, l, theta, stream));
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_to_internal(const mgpcg_problem *p, int level, const double *src, double *dst,
+                               hipStream_t stream) {
+    ST_TRY(check_level(p, level));
+    if (!src || !dst) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    DeviceGuard dg(p->device);
+    HIP_TRY(launch_permute(p, level, src, dst, true, stream));
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_to_natural(const mgpcg_problem *p, int level, const double *src, double *dst,
+                              hipStream_t stream) {
+    ST_TRY(check_level(p, level));
+    if (!src || !dst) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    DeviceGuard dg(p->device);
+    HIP_TRY(launch_permute(p, level, src, dst, false, stream));
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_spmv(const mgpcg_problem *p_, int level, const double *x, double *y, int layout,
+                        hipStream_t s) {
+    ST_TRY(check_level(p_, level));
+    ST_TRY(check_layout(layout));
+    if (!x || !y) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    DeviceGuard dg(p->device);
+    ST_TRY(ensure_scratch(p, level));
+    Level &Lv = p->lev[level];
+    const int64_t n = Lv.n * p->R;
+    const bool f64 = (level == 0 || p->mg_dtype == MGPCG_FP64);
+    const double *xi = x;
+    double *yi = y;
+    if (layout == MGPCG_LAYOUT_NATURAL) {
+        HIP_TRY(launch_permute(p, level, x, Lv.t0, true, s));
+        xi = Lv.t0;
+        yi = Lv.t1;
+    }
+    if (f64) {
+        HIP_TRY(launch_spmv<double>(p, level, Lv.val64, xi, yi, s));
+    } else {
+        HIP_TRY(launch_cast_d2f(xi, (float *)Lv.r, n, s));
+        HIP_TRY(launch_spmv<float>(p, level, Lv.val32, (const float *)Lv.r, (float *)Lv.z, s));
+        HIP_TRY(launch_cast_f2d((const float *)Lv.z, yi, n, s));
+    }
+    if (layout == MGPCG_LAYOUT_NATURAL) HIP_TRY(launch_permute(p, level, yi, y, false, s));
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_make_rhs_ones(const mgpcg_problem *p_, double *b, int layout, hipStream_t s) {
+    ST_TRY(check_problem(p_));
+    ST_TRY(check_layout(layout));
+    if (!b) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    DeviceGuard dg(p->device);
+    ST_TRY(ensure_scratch(p, 0));
+    Level &L0 = p->lev[0];
+    HIP_TRY(launch_fill_d(L0.t0, L0.n * p->R, 1.0, s));
+    if (layout == MGPCG_LAYOUT_NATURAL) {
+        HIP_TRY(launch_spmv<double>(p, 0, L0.val64, L0.t0, L0.t1, s));
+        HIP_TRY(launch_permute(p, 0, L0.t1, b, false, s));
+    } else {
+        HIP_TRY(launch_spmv<double>(p, 0, L0.val64, L0.t0, b, s));
+    }
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_gs_sweep(const mgpcg_problem *p_, int level, const double *r, double *z, int layout,
+                            hipStream_t s) {
+    ST_TRY(check_level(p_, level));
+    ST_TRY(check_layout(layout));
+    if (!r || !z) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    DeviceGuard dg(p->device);
+    return with_level_vectors(p, level, r, z, layout, s, true, [&](const void *rv, void *zv) {
+        if (p->mg_dtype == MGPCG_FP64)
+            return sweep<double>(p, level, p->lev[level].val64, (const double *)rv, (double *)zv, false,
+                                 nullptr, s);
+        return sweep<float>(p, level, p->lev[level].val32, (const float *)rv, (float *)zv, false, nullptr, s);
+    });
+}
+
+mgpcg_status mgpcg_restrict(const mgpcg_problem *p_, int level, const double *r, const double *z, double *rc,
+                            int layout, hipStream_t s) {
+    ST_TRY(check_level(p_, level, true));
+    ST_TRY(check_layout(layout));
+    if (!r || !z || !rc) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    DeviceGuard dg(p->device);
+    ST_TRY(ensure_scratch(p, level));
+    ST_TRY(ensure_scratch(p, level + 1));
+    Level &F = p->lev[level];
+    Level &C = p->lev[level + 1];
+    const int64_t nf = F.n * p->R, nc = C.n * p->R;
+    ST_TRY(in_vec(p, level, r, F.t0, layout, s));
+    ST_TRY(in_vec(p, level, z, F.t1, layout, s));
+    if (p->mg_dtype == MGPCG_FP64) {
+        HIP_TRY(launch_restrict<double>(p, level, F.val64, F.t0, F.t1, C.t2, s));
+    } else {
+        HIP_TRY(launch_cast_d2f(F.t0, (float *)F.r, nf, s));
+        HIP_TRY(launch_cast_d2f(F.t1, (float *)F.z, nf, s));
+        HIP_TRY(launch_restrict<float>(p, level, F.val32, (const float *)F.r, (const float *)F.z, (float *)C.r, s));
+        HIP_TRY(launch_cast_f2d((const float *)C.r, C.t2, nc, s));
+    }
+    return out_vec(p, level + 1, C.t2, rc, layout, s);
+}
+
+mgpcg_status mgpcg_prolong_add(const mgpcg_problem *p_, int level, const double *zc, double *z, int layout,
+                               hipStream_t s) {
+    ST_TRY(check_level(p_, level, true));
+    ST_TRY(check_layout(layout));
+    if (!zc || !z) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    DeviceGuard dg(p->device);
+    ST_TRY(ensure_scratch(p, level));
+    ST_TRY(ensure_scratch(p, level + 1));
+    Level &F = p->lev[level];
+    Level &C = p->lev[level + 1];
+    const int64_t nf = F.n * p->R, nc = C.n * p->R;
+    ST_TRY(in_vec(p, level + 1, zc, C.t0, layout, s));
+    ST_TRY(in_vec(p, level, z, F.t1, layout, s));
+    if (p->mg_dtype == MGPCG_FP64) {
+        HIP_TRY(launch_prolong<double>(p, level, C.t0, F.t1, s));
+    } else {
+        HIP_TRY(launch_cast_d2f(C.t0, (float *)C.z, nc, s));
+        HIP_TRY(launch_cast_d2f(F.t1, (float *)F.z, nf, s));
+        HIP_TRY(launch_prolong<float>(p, level, (const float *)C.z, (float *)F.z, s));
+        HIP_TRY(launch_cast_f2d((const float *)F.z, F.t1, nf, s));
+    }
+    return out_vec(p, level, F.t1, z, layout, s);
+}
+
+mgpcg_status mgpcg_mg_vcycle(const mgpcg_problem *p_, const double *r, double *z, int layout, hipStream_t s) {
+    ST_TRY(check_problem(p_));
+    ST_TRY(check_layout(layout));
+    if (!r || !z) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    DeviceGuard dg(p->device);
+    return with_level_vectors(p, 0, r, z, layout, s, false, [&](const void *rv, void *zv) {
+        if (p->mg_dtype == MGPCG_FP64) return vcycle<double>(p, (const double *)rv, (double *)zv, nullptr, s);
+        return vcycle<float>(p, (const float *)rv, (float *)zv, nullptr, s);
+    });
+}
+
+mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int max_iters, double rel_tol,
+                             double *history_host, int *iters_host, int layout, hipStream_t s) {
+    ST_TRY(check_problem(p));
+    ST_TRY(check_layout(layout));
+    if (!b || !x) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    if (max_iters < 0) return fail(MGPCG_ERR_INVALID_ARG, "max_iters must be >= 0");
+    if (!(rel_tol >= 0.0) || !isfinite(rel_tol)) return fail(MGPCG_ERR_INVALID_ARG, "rel_tol must be finite and >= 0");
+    DeviceGuard dg(p->device);
+    const int S = p->S;
+    const int64_t n = p->lev[0].n * p->R;
+    if (max_iters > p->hist_cap) {
+        int cap = std::max(max_iters, 64);
+        double *h = nullptr;
+        ST_TRY(dalloc(&h, (int64_t)S * cap));
+        HIP_TRY(hipStreamSynchronize(s));
+        dfree(p->hist);
+        p->hist = h;
+        p->hist_cap = cap;
+        if (p->iter_graph) {
+            (void)hipGraphExecDestroy(p->iter_graph);
+            p->iter_graph = nullptr;
+        }
+    }
+    p->last_max_iters = max_iters;
+    if (p->iter_graph && p->last_tol != rel_tol) {
+        (void)hipGraphExecDestroy(p->iter_graph);
+        p->iter_graph = nullptr;
+    }
+    p->last_tol = rel_tol;
+
+    ST_TRY(in_vec(p, 0, b, p->b, layout, s));
+    ST_TRY(in_vec(p, 0, x, p->x, layout, s));
+    Scalars &sc = p->sc;
+    HIP_TRY(launch_fill_u(sc.tickets, (int64_t)kTicketKinds * p->G, 0u, s));
+    HIP_TRY(launch_fill_i(sc.done, S, 0, s));
+    HIP_TRY(launch_fill_i(sc.status, S, 0, s));
+    HIP_TRY(launch_fill_i(sc.iter, S, 0, s));
+    HIP_TRY(launch_fill_i(sc.ndone, 1, 0, s));
+    HIP_TRY(launch_fill_d(sc.rho_old, S, 0.0, s));
+    HIP_TRY(launch_fill_d(p->hist, (int64_t)S * p->hist_cap, 0.0, s));
+    HIP_TRY(launch_fill_d(p->p, n, 0.0, s));
+    HIP_TRY(launch_init_residual(p, s));
+
+    if (p->use_graph && !p->iter_graph && max_iters > 0) {
+        if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = cg_iteration(p, rel_tol, p->cap_stream);
+        hipError_t ee = hipStreamEndCapture(p->cap_stream, &graph);
+        if (ce != hipSuccess) return hip_fail(ce, "capturing the CG iteration");
+        if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+        hipError_t ie = hipGraphInstantiate(&p->iter_graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            p->iter_graph = nullptr;
+            return hip_fail(ie, "hipGraphInstantiate");
+        }
+    }
+    const bool check = rel_tol > 0.0;
+    const int check_every = p->lev[0].n * p->R >= (1 << 20) ? 1 : 4;
+    for (int it = 0; it < max_iters; ++it) {
+        if (check && it > 0 && it % check_every == 0) {
+            HIP_TRY(hipMemcpyAsync(p->pinned_ndone, sc.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (*p->pinned_ndone >= S) break;
+        }
+        if (p->iter_graph) HIP_TRY(hipGraphLaunch(p->iter_graph, s));
+        else HIP_TRY(cg_iteration(p, rel_tol, s));
+    }
+    ST_TRY(out_vec(p, 0, p->x, x, layout, s));
+    if (!history_host && !iters_host && rel_tol == 0.0) return MGPCG_OK;
+    return fetch_result(p, max_iters, history_host, iters_host, s);
+}
+
+mgpcg_status mgpcg_solve_result(mgpcg_problem *p, int max_iters, double *history_host, int *iters_host,
+                                hipStream_t s) {
+    ST_TRY(check_problem(p));
+    if (max_iters < 0) return fail(MGPCG_ERR_INVALID_ARG, "max_iters must be >= 0");
+    DeviceGuard dg(p->device);
+    return fetch_result(p, max_iters, history_host, iters_host, s);
+}
+
+mgpcg_status mgpcg_theta_grad(const mgpcg_problem *p, const double *lambda, const double *x,
+                              const double *theta, double *grad, hipStream_t s) {
+    ST_TRY(check_problem(p));
+    if (!lambda || !x || !theta || !grad) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    if (p->R != 1) return fail(MGPCG_ERR_INVALID_ARG, "theta_grad needs nrhs == 1");
+    DeviceGuard dg(p->device);
+    HIP_TRY(launch_theta_grad(lambda, x, theta, grad, p->lev[0].n, s));
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_set_graph_mode(mgpcg_problem *p, int on) {
+    ST_TRY(check_problem(p));
+    p->use_graph = on ? 1 : 0;
+    if (!on && p->iter_graph) {
+        (void)hipGraphExecDestroy(p->iter_graph);
+        p->iter_graph = nullptr;
+    }
+    return MGPCG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal structures of the MI355X MG-PCG library (not part of the ABI).
+//
+// Data layout in HBM (per level l, all grids of the problem):
+//   rows are colour-major across grids: for colour k = 0..7, for grid g, the
+//   points of grid g with colour k in lexicographic order of their half-grid
+//   coordinates (ix>>1, iy>>1, iz>>1).  Consecutive rows of one colour are
+//   consecutive points along x, so the neighbour in a fixed stencil direction
+//   of consecutive rows is again consecutive: every gather of the sweep reads
+//   near-contiguous memory.
+//   The operator is 27-slot ELL, slot-major: value and column of slot s of row
+//   i at [s*n + i]; slot s is direction (dx,dy,dz) = (s%3-1, s/3%3-1, s/9-1),
+//   i.e. ascending natural column order; slot 13 is the diagonal; a missing
+//   neighbour is a padding slot with value 0 and column i.
+//   Vectors with R right-hand sides are interleaved: element (row i, rhs v) at
+//   i*R + v.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "mgpcg.h"
+
+namespace mg {
+
+constexpr int kW = 27;        // ELL width (3x3x3 stencil)
+constexpr int kCentre = 13;   // slot of the diagonal
+constexpr int kBlock = 256;   // threads per workgroup
+constexpr int kRedElems = 4096;  // row*rhs elements per reduction block
+
+// One workgroup's share of rows: [row0, row0+count), all in grid `grid`.
+struct Seg {
+    int64_t row0;
+    int32_t count;
+    int32_t grid;
+};
+
+struct LevelGrid {  // one grid at one level
+    int nx, ny, nz;
+    int ncol;            // colours of this grid (8 unless a dim is 1)
+    int64_t nat_off;     // first row of this grid in the natural packed order
+    int64_t seg_off[8];  // first internal row of (colour k, this grid)
+    int64_t seg_len[8];  // rows of (colour k, this grid)
+    int inj_colour;      // colour holding the injection points (2jx,2jy,2jz)
+};
+
+struct Level {
+    int64_t n = 0;       // rows, all grids
+    int64_t nnz = 0;     // structural nonzeros
+    int ncol = 0;        // colour passes (max over grids)
+    std::vector<LevelGrid> grids;
+    std::vector<int64_t> coff;  // ncol+1: internal row range of each colour (all grids)
+
+    double *val64 = nullptr;  // [27][n], FP64 operator (level 0 always; all levels if FP64 V-cycle)
+    float *val32 = nullptr;   // [27][n], FP32 operator (FP32 V-cycle)
+    int32_t *col = nullptr;   // [27][n]
+    int32_t *perm = nullptr;  // natural packed row -> internal row
+    int32_t *iperm = nullptr; // internal row -> natural packed row
+    int32_t *grid_of_nat = nullptr;  // natural packed row -> grid (only when G > 1)
+
+    // colour-pass tables: entries of colour k are pass_tab[pass_first[k] .. pass_first[k+1])
+    Seg *pass_tab = nullptr;
+    std::vector<int> pass_first;
+    uint32_t zi_skip[8] = {0};  // zero-start forward pass: slots whose neighbour is not yet written
+    bool zs_ok = true;          // the zero-start pass is valid for every grid of the level
+
+    // injection to level+1, sorted by fine internal row
+    int32_t *inj_fine = nullptr;
+    int32_t *inj_coarse = nullptr;
+    int64_t n_inj = 0;
+
+    // V-cycle workspaces in the V-cycle precision (n*R elements)
+    void *r = nullptr;
+    void *z = nullptr;
+    // FP64 scratch for the per-level API entry points (n*R elements each)
+    double *t0 = nullptr, *t1 = nullptr, *t2 = nullptr;
+};
+
+struct Scalars {  // per-system CG state, device arrays of S entries
+    double *rho, *rho_old, *alpha, *beta, *nr0, *pq;
+    int *iter, *done, *status;
+    int *ndone;          // one counter: systems finished
+    unsigned *tickets;   // kTicketKinds * G
+    double *partials;    // reduction blocks * R
+};
+constexpr int kTicketKinds = 4;
+
+}  // namespace mg
+
+struct mgpcg_problem {
+    int device = 0;
+    int G = 1, R = 1, S = 1, L = 1;
+    int mg_dtype = MGPCG_FP64;
+    int colour_order = 0;
+    std::vector<int> dims0;  // 3*G, level 0
+    std::vector<mg::Level> lev;
+
+    // device copies of small tables
+    int *d_dims0 = nullptr;        // 3*G
+    int64_t *d_natoff0 = nullptr;  // G+1 natural offsets at level 0
+    std::vector<int64_t *> d_natoff;  // per level, G+1
+
+    // level-0 reduction table (grid-homogeneous segments, grouped by grid)
+    mg::Seg *red_tab = nullptr;
+    int n_red = 0;
+    int *red_gb = nullptr;   // G+1: first reduction block of each grid
+    std::vector<int> red_gb_host;
+
+    // CG vectors, level 0, internal layout, n0*R doubles
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr;
+    mg::Scalars sc{};
+    double *hist = nullptr;  // S * hist_cap
+    int hist_cap = 0;
+    int last_max_iters = 0;
+    double last_tol = 0.0;
+
+    int *pinned_ndone = nullptr;  // host-pinned mirror for convergence checks
+
+    // captured iteration graph
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t iter_graph = nullptr;
+    int use_graph = 1;
+};

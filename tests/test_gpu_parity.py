@@ -1,0 +1,319 @@
+"""GPU parity: every hot-path step through the C ABI against the CPU oracle.
+
+Per-kernel results (SpMV, coloured sweep, restriction, prolongation, the
+whole V-cycle) are compared bit for bit: the library disables FP contraction
+and sums each row in the oracle's order, so the same IEEE operations happen
+on both sides.  CG adds reductions whose summation order differs (tree on the
+GPU, sequential in the oracle), so residual histories are compared with the
+rule |h_gpu - h_ora| <= 1e-12 * h_ora + 1e-20 (the relative 1e-12 target,
+with an absolute floor for entries that have reached the rounding regime).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2304_08232_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def mg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_08232_amd import mgpcg
+    mgpcg.lib()
+    return mgpcg
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def hist_ok(h_gpu, h_ora):
+    h_gpu, h_ora = np.asarray(h_gpu), np.asarray(h_ora)
+    assert h_gpu.shape == h_ora.shape, (h_gpu.shape, h_ora.shape)
+    bad = np.abs(h_gpu - h_ora) > 1e-12 * h_ora + 1e-20
+    assert not bad.any(), f"history mismatch at {np.nonzero(bad)[0][:5]}: {h_gpu[bad][:3]} vs {h_ora[bad][:3]}"
+
+
+DIMS = [(16, 16, 16), (24, 16, 32), (32, 8, 16)]
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_sizes_match(mg, dims):
+    o = Oracle(*dims, levels=4)
+    p = mg.Problem(dims, levels=4)
+    for l in range(4):
+        assert p.n(l) == o.n(l)
+        assert p.nnz(l) == o.nnz(l)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_layout_round_trip(mg, dims):
+    p = mg.Problem(dims, levels=4)
+    for l in range(4):
+        v = dev(inputs.uniform(20 + l, p.n(l)))
+        w = p.to_natural(p.to_internal(v, l), l)
+        assert torch.equal(v, w)
+        assert not torch.equal(v, p.to_internal(v, l)) or p.n(l) <= 8
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("order", [0, 1])
+def test_kernels_bitwise_each_level(mg, dims, order):
+    o = Oracle(*dims, levels=4, colour_order=order)
+    p = mg.Problem(dims, levels=4, colour_order=order)
+    for l in range(4):
+        n = o.n(l)
+        x = inputs.uniform(100 + l, n)
+        z0 = inputs.uniform(200 + l, n)
+        # SpMV
+        np.testing.assert_array_equal(host(p.spmv(dev(x), level=l)), o.spmv(x, level=l))
+        # one symmetric coloured sweep from a nonzero z
+        np.testing.assert_array_equal(host(p.gs_sweep(dev(x), dev(z0), level=l)), o.sgs(x, z0, level=l))
+        if l + 1 < 4:
+            np.testing.assert_array_equal(host(p.restrict(dev(x), dev(z0), level=l)),
+                                          o.restrict(x, z0, level=l))
+            zc = inputs.uniform(300 + l, o.n(l + 1))
+            np.testing.assert_array_equal(host(p.prolong_add(dev(zc), dev(z0), level=l)),
+                                          o.prolong_add(zc, z0, level=l))
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("order", [0, 1])
+def test_vcycle_bitwise(mg, dims, order):
+    o = Oracle(*dims, levels=4, colour_order=order)
+    p = mg.Problem(dims, levels=4, colour_order=order)
+    for seed in (1, 2):
+        r = inputs.uniform(seed, o.n())
+        np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle(r))
+
+
+def test_rhs_ones(mg):
+    o = Oracle(16, 16, 16)
+    p = mg.Problem((16, 16, 16))
+    b = host(p.make_rhs_ones())
+    np.testing.assert_array_equal(b, o.spmv(np.ones(o.n())))
+    bi = p.make_rhs_ones(layout=mg.INTERNAL)
+    np.testing.assert_array_equal(host(p.to_natural(bi)), b)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_pcg_16cubed_history(mg, order):
+    o = Oracle(16, 16, 16, colour_order=order)
+    p = mg.Problem((16, 16, 16), colour_order=order)
+    b = o.spmv(np.ones(o.n()))
+    xo, ho, ito, sto = o.pcg(b, max_iters=50)
+    x, h, its, st = p.solve(dev(b), max_iters=50)
+    assert st == mg.OK and its[0] == 50 and ito == 50
+    hist_ok(h[0], ho)
+    xg = host(x)
+    assert np.linalg.norm(xg - xo) <= 1e-12 * np.linalg.norm(xo)
+    assert np.abs(xg - 1.0).max() < 1e-12
+
+
+def test_pcg_tolerance_stop_and_status(mg):
+    o = Oracle(24, 16, 32)
+    p = mg.Problem((24, 16, 32))
+    b = inputs.uniform(5, o.n())
+    xo, ho, ito, sto = o.pcg(b, max_iters=200, tol=1e-9)
+    x, h, its, st = p.solve(dev(b), max_iters=200, tol=1e-9)
+    assert st == mg.OK and sto == 0
+    assert its[0] == ito
+    hist_ok(h[0, :ito], ho)
+    assert np.all(h[0, ito:] == 0)
+    assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+    # not converged within max_iters
+    x, h, its, st = p.solve(dev(b), max_iters=3, tol=1e-12)
+    assert st == mg.NOT_CONVERGED and its[0] == 3
+    # zero right-hand side: zero iterations
+    x, h, its, st = p.solve(dev(np.zeros(o.n())), max_iters=10, tol=1e-9)
+    assert st == mg.OK and its[0] == 0 and float(host(x).max()) == 0.0
+    # breakdown: NaN in b
+    bn = b.copy()
+    bn[7] = np.nan
+    x, h, its, st = p.solve(dev(bn), max_iters=10, tol=0.0)
+    assert st == mg.ERR_BREAKDOWN and its[0] == 0
+
+
+def test_pcg_nonzero_x0(mg):
+    o = Oracle(16, 16, 16)
+    p = mg.Problem((16, 16, 16))
+    b = inputs.uniform(6, o.n())
+    x0 = inputs.uniform(7, o.n())
+    xo, ho, _, _ = o.pcg(b, x0=x0, max_iters=20)
+    x, h, its, st = p.solve(dev(b), x0=dev(x0), max_iters=20)
+    hist_ok(h[0], ho)
+    assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+
+
+def test_graph_and_eager_identical_and_deterministic(mg):
+    p = mg.Problem((16, 16, 16))
+    b = p.make_rhs_ones()
+    outs = []
+    for mode in (1, 1, 0, 1):
+        p.set_graph_mode(mode)
+        x, h, its, st = p.solve(b, max_iters=30)
+        outs.append((host(x), h.copy()))
+        # eager work and a sync between graph replays
+        torch.cuda.synchronize()
+        _ = p.spmv(x)
+    for xg, hg in outs[1:]:
+        np.testing.assert_array_equal(xg, outs[0][0])
+        np.testing.assert_array_equal(hg, outs[0][1])
+
+
+def test_async_solve_and_result(mg):
+    p = mg.Problem((16, 16, 16))
+    b = p.make_rhs_ones(layout=mg.INTERNAL)
+    x = p.zeros()
+    assert p.solve_async(b, x, max_iters=25, layout=mg.INTERNAL) == mg.OK
+    h = np.zeros(25)
+    its = np.zeros(1, np.int32)
+    assert mg.mgpcg_solve_result(p.h, 25, h, its) == mg.OK
+    x2, h2, its2, _ = p.solve(p.to_natural(b), max_iters=25)
+    np.testing.assert_array_equal(h, h2[0])
+    np.testing.assert_array_equal(host(p.to_natural(x)), host(x2))
+
+
+def test_error_paths(mg):
+    p = mg.Problem((16, 16, 16))
+    v = p.zeros()
+    with pytest.raises(mg.MGPCGError) as e:
+        p.spmv(v, level=4)
+    assert e.value.status == -1
+    with pytest.raises(mg.MGPCGError):
+        p.restrict(v, v, level=3)
+    with pytest.raises(mg.MGPCGError):
+        mg.mgpcg_spmv(p.h, 0, v, v, layout=7)
+    with pytest.raises(mg.MGPCGError):
+        mg.mgpcg_pcg_solve(p.h, v, v, -1)
+    with pytest.raises(mg.MGPCGError) as e:
+        mg.Problem((12, 16, 16))
+    assert e.value.status == -2
+
+
+# ---------------------------------------------------------------- FP32 V-cycle
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_fp32_vcycle_bitwise(mg, order):
+    dims = (24, 16, 32)
+    o = Oracle(*dims, colour_order=order)
+    p = mg.Problem(dims, mg_dtype="fp32", colour_order=order)
+    r = inputs.uniform(8, o.n())
+    np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle32(r))
+    for l in range(4):
+        n = o.n(l)
+        rr = inputs.uniform(30 + l, n).astype(np.float32)
+        zz = inputs.uniform(40 + l, n).astype(np.float32)
+        got = host(p.gs_sweep(dev(rr.astype(np.float64)), dev(zz.astype(np.float64)), level=l))
+        np.testing.assert_array_equal(got, o.sgs32(rr, zz, level=l).astype(np.float64))
+
+
+def test_fp32_pcg_matches_oracle(mg):
+    dims = (32, 32, 32)
+    o = Oracle(*dims)
+    p = mg.Problem(dims, mg_dtype="fp32")
+    b = o.spmv(np.ones(o.n())) + inputs.perturbation(3, o.n())
+    xo, ho, ito, _ = o.pcg(b, max_iters=200, tol=1e-9, precond=2)
+    x, h, its, st = p.solve(dev(b), max_iters=200, tol=1e-9)
+    assert st == mg.OK and its[0] == ito
+    hist_ok(h[0, :ito], ho)
+    x64, _, it64, _ = o.pcg(b, max_iters=200, tol=1e-9, precond=1)
+    # same answer as the FP64-preconditioned solve to the solver tolerance
+    assert np.linalg.norm(host(x) - x64) <= 1e-8 * np.linalg.norm(x64)
+
+
+# -------------------------------------------------------- batched / multi-RHS
+
+def test_batched_grids(mg):
+    dims = [(16, 16, 16), (24, 16, 32), (8, 16, 8)]
+    p = mg.Problem(dims, levels=4)
+    oras = [Oracle(*d) for d in dims]
+    sizes = [o.n() for o in oras]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    b = inputs.batch_rhs(9, sizes)
+    # V-cycle of all grids at once equals each grid's own
+    z = host(p.vcycle(dev(b)))
+    for g, o in enumerate(oras):
+        np.testing.assert_array_equal(z[offs[g]:offs[g + 1]], o.vcycle(b[offs[g]:offs[g + 1]]))
+    # coarse levels too
+    for l in range(1, 4):
+        nl = [o.n(l) for o in oras]
+        ol = np.concatenate([[0], np.cumsum(nl)])
+        r = inputs.batch_rhs(10 + l, nl)
+        zz = inputs.batch_rhs(20 + l, nl)
+        got = host(p.gs_sweep(dev(r), dev(zz), level=l))
+        for g, o in enumerate(oras):
+            np.testing.assert_array_equal(got[ol[g]:ol[g + 1]], o.sgs(r[ol[g]:ol[g + 1]], zz[ol[g]:ol[g + 1]], level=l))
+    x, h, its, st = p.solve(dev(b), max_iters=200, tol=1e-9)
+    assert st == mg.OK
+    xg = host(x)
+    for g, o in enumerate(oras):
+        xo, ho, ito, _ = o.pcg(b[offs[g]:offs[g + 1]], max_iters=200, tol=1e-9)
+        assert its[g] == ito
+        hist_ok(h[g, :ito], ho)
+        assert np.all(h[g, ito:] == 0)
+        np.testing.assert_allclose(xg[offs[g]:offs[g + 1]], xo, rtol=0, atol=1e-12 * np.abs(xo).max())
+
+
+@pytest.mark.parametrize("nrhs", [2, 16])
+def test_multi_rhs(mg, nrhs):
+    dims = (16, 16, 16)
+    o = Oracle(*dims)
+    n = o.n()
+    p = mg.Problem(dims, nrhs=nrhs)
+    B = inputs.multi_rhs(41, nrhs, n)
+    Z = host(p.vcycle(dev(B)))
+    Y = host(p.spmv(dev(B)))
+    for v in range(nrhs):
+        np.testing.assert_array_equal(Z[v * n:(v + 1) * n], o.vcycle(B[v * n:(v + 1) * n]))
+        np.testing.assert_array_equal(Y[v * n:(v + 1) * n], o.spmv(B[v * n:(v + 1) * n]))
+    x, h, its, st = p.solve(dev(B), max_iters=100, tol=1e-9)
+    assert st == mg.OK
+    X = host(x)
+    for v in range(nrhs):
+        xo, ho, ito, _ = o.pcg(B[v * n:(v + 1) * n], max_iters=100, tol=1e-9)
+        assert its[v] == ito
+        hist_ok(h[v, :ito], ho)
+        np.testing.assert_allclose(X[v * n:(v + 1) * n], xo, rtol=0, atol=1e-12 * np.abs(xo).max())
+
+
+# ---------------------------------------------------------------- full size
+
+@pytest.fixture(scope="module")
+def p128(mg):
+    return mg.Problem((128, 128, 128), levels=4)
+
+
+def test_128cubed_kernels_bitwise(mg, p128):
+    o = Oracle(128, 128, 128)
+    x = inputs.uniform(2, o.n())
+    np.testing.assert_array_equal(host(p128.spmv(dev(x))), o.spmv(x))
+    np.testing.assert_array_equal(host(p128.vcycle(dev(x))), o.vcycle(x))
+    z0 = inputs.uniform(3, o.n())
+    np.testing.assert_array_equal(host(p128.gs_sweep(dev(x), dev(z0))), o.sgs(x, z0))
+
+
+def test_128cubed_pcg_history_golden(mg, p128):
+    gold = json.load(open(os.path.join(HERE, "golden", "pcg_128cubed_fp64.json")))
+    b = p128.make_rhs_ones()
+    x, h, its, st = p128.solve(b, max_iters=50)
+    assert st == mg.OK and its[0] == 50
+    hist_ok(h[0], np.array(gold["history"]))
+    xg = host(x)
+    idx = np.array(gold["sample_index"])
+    np.testing.assert_allclose(xg[idx], np.array(gold["sample_x"]), rtol=1e-12, atol=0)
+    assert abs(np.abs(xg - 1.0).max() - gold["max_abs_err"]) <= 1e-12
