@@ -33,10 +33,14 @@ static double logistic(double t) {
     return 1.0 / (1.0 + exp(-t));
 }
 
+/* Inner product (Sec. II-C).  Its definition is the exact sum; a left to
+ * right FP64 sum over millions of terms can be off by ~1e-13 relative, which
+ * CG amplifies past a 1e-12 comparison bar, so the terms are accumulated in
+ * the x87 extended format (64-bit significand) and rounded once at the end. */
 double ora_dot(int64_t n, const double *a, const double *b) {
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
-    return s;
+    long double s = 0.0L;
+    for (int64_t i = 0; i < n; ++i) s += (long double)a[i] * (long double)b[i];
+    return (double)s;
 }
 
 /* ---------------------------------------------------- problem generation */

@@ -93,7 +93,7 @@ int ora_pcg(const ora_hier *h, const double *b, double *x, int max_iters,
 void ora_theta_grad(int64_t n, const double *lambda, const double *x,
                     const double *theta, double *grad);
 
-/* Sequential sums used by CG (left to right). */
+/* Inner product used by CG: sequential, extended-precision accumulator. */
 double ora_dot(int64_t n, const double *a, const double *b);
 
 #endif
