@@ -65,6 +65,7 @@ def time_solves(torch, mg, prob, b, x, steps, warmup, iters):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
+        x.zero_()  # x0 = 0 for every step
         prob.solve_async(b, x, max_iters=iters, layout=mg.INTERNAL)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
@@ -106,7 +107,7 @@ def dominant_kernel(torch, mg, prob, reps=20):
     return e0.elapsed_time(e1) * 1e-3 / launches, launches
 
 
-def cpu_baseline(iters=5):
+def cpu_baseline(iters=25):
     from oracle import Oracle
     from paper_2304_08232_amd import perfmodel
     o = Oracle(*GRID, levels=LEVELS)

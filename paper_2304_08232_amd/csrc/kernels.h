@@ -14,10 +14,16 @@ hipError_t launch_permute(const mgpcg_problem *P, int level, const double *src, 
 template <typename T>
 hipError_t launch_spmv(const mgpcg_problem *P, int level, const T *val, const T *x, T *y, hipStream_t s);
 
-// one colour pass of the coloured Gauss-Seidel smoother
+// zero-start skip mask compiled into the kernels for colour k (standard colouring)
+uint32_t standard_zs_mask(int k, int order);
+
+// one colour pass of the coloured Gauss-Seidel smoother; mode: plain,
+// zero start, or with the restriction / refinement of the level fused in
+// (`coarse` is then the coarse-level rc or zc)
+enum { kPassPlain = 0, kPassZeroStart = 1, kPassRestrict = 2, kPassProlong = 3 };
 template <typename T>
-hipError_t launch_pass(const mgpcg_problem *P, int level, int k, bool zero_start, const T *val,
-                       const T *r, T *z, const int *done, hipStream_t s);
+hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
+                       const int *done, T *coarse, hipStream_t s);
 
 template <typename T>
 hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, const T *r, const T *z,

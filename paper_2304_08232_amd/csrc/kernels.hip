@@ -52,6 +52,65 @@ __device__ __forceinline__ int find_grid(const int64_t *off, int G, int64_t q) {
 
 inline int nblocks(int64_t work) { return (int)((work + kBlock - 1) / kBlock); }
 
+// Load helper: streaming (non-temporal) loads for operators far larger than
+// the caches, ordinary loads otherwise so that coarse operators stay resident.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// sum_j a_ij x_j over the 27 slots of row i, in slot order (ascending natural
+// column order), skipping padding slots (value 0).  All value and column
+// loads of the row are issued before the dependent gathers, so a wave keeps
+// 54 streaming loads and then 27 gathers in flight.  Slots whose bit is set
+// in the compile-time SKIP mask are left out entirely (their x is known to be
+// zero); the diagonal value is always loaded and returned in d.
+template <typename T, int R, uint32_t SKIP, bool NT>
+__device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *__restrict__ col, int64_t n,
+                                     int64_t i, const T *x, int v, T &d) {
+    T a[kW];
+    int32_t c[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
+        c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
+    }
+    d = a[kCentre];
+    T xv[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        xv[s] = (!sk && a[s] != T(0)) ? x[(int64_t)c[s] * R + v] : T(0);
+    }
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        if (!sk && a[s] != T(0)) acc = acc + a[s] * xv[s];
+    }
+    return acc;
+}
+
+// Zero-start skip mask of colour k for the standard colouring of grids whose
+// extents are all >= 2: colour number c has parity code c (order 0) or 7-c
+// (order 1), the neighbour in direction d has parity code pc ^ parity(d), and
+// a slot is skipped when that neighbour's colour number is >= k (not yet
+// written in the forward sweep; this includes the diagonal).
+constexpr uint32_t zs_mask(int k, int order) {
+    uint32_t m = 0;
+    const int pc = order ? 7 - k : k;
+    for (int s = 0; s < kW; ++s) {
+        const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+        const int pd = (dx != 0 ? 1 : 0) | (dy != 0 ? 2 : 0) | (dz != 0 ? 4 : 0);
+        const int nb = pc ^ pd;
+        const int nbc = order ? 7 - nb : nb;
+        if (nbc >= k) m |= 1u << s;
+    }
+    return m;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ setup
@@ -155,15 +214,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const T *__restrict_
     if (gid >= n * R) return;
     int64_t i = gid / R;
     int v = (int)(gid % R);
-    T acc = 0;
-#pragma unroll
-    for (int sl = 0; sl < kW; ++sl) {
-        int64_t e = (int64_t)sl * n + i;
-        T a = ld_nt(val + e);
-        int32_t c = ld_nt(col + e);
-        if (a != T(0)) acc = acc + a * x[(int64_t)c * R + v];
-    }
-    y[gid] = acc;
+    T d;
+    y[gid] = row_sum<T, R, 0u, true>(val, col, n, i, x, v, d);
 }
 
 template <typename T>
@@ -184,66 +236,169 @@ template hipError_t launch_spmv<float>(const mgpcg_problem *, int, const float *
 // One colour of the coloured Gauss-Seidel pass (Listing 3 of the paper, the
 // masked product and the update fused).  Rows of one colour are independent,
 // so the update is done in place: a row reads only other colours and itself.
-// ZS (zero start): z is all zeros before this sweep, so only neighbours
-// already written in this sweep (colours < k) are read; `skip` holds the
-// slots whose neighbour cannot have been written yet (including the
-// diagonal), and z_i itself is taken as 0.  The z array needs no clearing.
-template <typename T, int R, bool ZS>
+//
+// SKIP != 0 (zero start): z is all zeros before this sweep, so only
+// neighbours already written in this sweep (colours < k) are read and z_i
+// itself is taken as 0; the z array needs no clearing.
+//
+// MODE 1 (last pass of the pre-smoother when the colour swept last is the
+// injection set): after its update, each row is an injection point whose
+// neighbours are final, so the thread also forms the restricted residual
+// rc = r_i - sum_j a_ij z_j (new z_i at the centre, same slot order as a
+// separate residual pass) and writes it to the coarse level.
+// MODE 2 (first pass of the post-smoother, same condition): the refinement
+// z_i += zc is applied on the fly; the rows of this colour are the only
+// readers of the refined values.
+//
+// Rows come from the segment table when the problem has several grids;
+// otherwise workgroup b owns rows [row_base + b*rows, ...) of the colour.
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE>
 __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col,
                                                  const T *__restrict__ r, T *z,
-                                                 const Seg *__restrict__ tab, uint32_t skip,
-                                                 const int *__restrict__ done) {
-    Seg e = tab[xcd_remap(blockIdx.x, gridDim.x)];
-    int rl = threadIdx.x / R, v = threadIdx.x % R;
-    if (rl >= e.count) return;
-    if (done && done[e.grid * R + v]) return;
-    int64_t i = e.row0 + rl;
-    T acc = 0, d = 0;
-#pragma unroll
-    for (int sl = 0; sl < kW; ++sl) {
-        int64_t ei = (int64_t)sl * n + i;
-        if (ZS && ((skip >> sl) & 1u)) {
-            if (sl == kCentre) d = ld_nt(val + ei);
-            continue;
-        }
-        T a = ld_nt(val + ei);
-        int32_t c = ld_nt(col + ei);
-        if (sl == kCentre) d = a;
-        if (a != T(0)) acc = acc + a * z[(int64_t)c * R + v];
+                                                 const Seg *__restrict__ tab, int64_t row_base,
+                                                 int64_t row_end, const int *__restrict__ done,
+                                                 T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t row0, count;
+    int grid;
+    if (tab) {
+        const Seg e = tab[b];
+        row0 = e.row0;
+        count = e.count;
+        grid = e.grid;
+    } else {
+        row0 = row_base + (int64_t)b * (kBlock / R);
+        count = row_end - row0;
+        grid = 0;
     }
-    int64_t o = i * R + v;
-    T zi = ZS ? T(0) : z[o];
-    z[o] = (r[o] - acc + zi * d) / d;
+    const int rl = threadIdx.x / R, v = threadIdx.x % R;
+    if (rl >= count) return;
+    if (done && done[grid * R + v]) return;
+    const int64_t i = row0 + rl;
+    const int64_t o = i * R + v;
+
+    T a[kW];
+    int32_t c[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
+        c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
+    }
+    const T d = a[kCentre];
+    const T rv = r[o];
+    T zc = T(0);
+    int64_t co = 0;
+    if (MODE != 0) co = (int64_t)inj_coarse[i - row_base] * R + v;
+    if (MODE == 2) zc = coarse[co];
+    T xv[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        xv[s] = (!sk && a[s] != T(0)) ? z[(int64_t)c[s] * R + v] : T(0);
+    }
+    // z_i before this pass (refined in MODE 2); 0 on a zero start
+    const T zi = SKIP ? T(0) : (MODE == 2 ? xv[kCentre] + zc : xv[kCentre]);
+    if (MODE == 2) xv[kCentre] = zi;
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        if (!sk && a[s] != T(0)) acc = acc + a[s] * xv[s];
+    }
+    const T znew = (rv - acc + zi * d) / d;
+    z[o] = znew;
+    if (MODE == 1) {
+        xv[kCentre] = znew;
+        T f = 0;
+#pragma unroll
+        for (int s = 0; s < kW; ++s)
+            if (a[s] != T(0)) f = f + a[s] * xv[s];
+        coarse[co] = rv - f;
+    }
 }
 
-template <typename T>
-hipError_t launch_pass(const mgpcg_problem *P, int level, int k, bool zero_start, const T *val,
-                       const T *r, T *z, const int *done, hipStream_t s) {
-    const Level &L = P->lev[level];
-    int first = L.pass_first[k], cnt = L.pass_first[k + 1] - first;
-    if (cnt == 0) return hipSuccess;
-    const Seg *tab = L.pass_tab + first;
-    if (zero_start) {
-        MG_DISPATCH_R(P->R, (k_pass<T, RR, true><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, r, z, tab,
-                                                                         L.zi_skip[k], done)));
-    } else {
-        MG_DISPATCH_R(P->R, (k_pass<T, RR, false><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, r, z, tab,
-                                                                          0u, done)));
+template <typename T, int R, bool NT>
+static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T *val, const int32_t *col,
+                    const T *r, T *z, const Seg *tab, int64_t rb, int64_t re, const int *done) {
+#define MG_ZS_CASE(K, O)                                                                              \
+    case K + 8 * O:                                                                                   \
+        k_pass<T, R, zs_mask(K, O), NT, 0><<<cnt, kBlock, 0, s>>>(n, val, col, r, z, tab, rb, re, done,  \
+                                                                  nullptr, nullptr);                \
+        break;
+    switch (k + 8 * order) {
+        MG_ZS_CASE(0, 0) MG_ZS_CASE(1, 0) MG_ZS_CASE(2, 0) MG_ZS_CASE(3, 0)
+        MG_ZS_CASE(4, 0) MG_ZS_CASE(5, 0) MG_ZS_CASE(6, 0) MG_ZS_CASE(7, 0)
+        MG_ZS_CASE(0, 1) MG_ZS_CASE(1, 1) MG_ZS_CASE(2, 1) MG_ZS_CASE(3, 1)
+        MG_ZS_CASE(4, 1) MG_ZS_CASE(5, 1) MG_ZS_CASE(6, 1) MG_ZS_CASE(7, 1)
+        default: break;
     }
+#undef MG_ZS_CASE
+}
+
+uint32_t standard_zs_mask(int k, int order) { return zs_mask(k, order); }
+
+template <typename T>
+hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
+                       const int *done, T *coarse, hipStream_t s) {
+    const Level &L = P->lev[level];
+    const int R = P->R;
+    const Seg *tab = nullptr;
+    int cnt;
+    const int64_t rb = L.coff[k], re = L.coff[k + 1];
+    if (P->G > 1) {
+        const int first = L.pass_first[k];
+        cnt = L.pass_first[k + 1] - first;
+        tab = L.pass_tab + first;
+    } else {
+        cnt = (int)((re - rb + kBlock / R - 1) / (kBlock / R));
+    }
+    if (cnt == 0) return hipSuccess;
+    const int32_t *ic = L.inj_coarse;
+    if (mode == kPassZeroStart) {
+        if (!L.zs_std || (R != 1 && R != 16)) return hipErrorInvalidValue;
+        const int ord = P->colour_order;
+        if (L.stream_nt) {
+            if (R == 1) pass_zs<T, 1, true>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
+            else pass_zs<T, 16, true>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
+        } else {
+            if (R == 1) pass_zs<T, 1, false>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
+            else pass_zs<T, 16, false>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
+        }
+        return hipGetLastError();
+    }
+#define MG_PASS_MODE(M)                                                                                \
+    if (L.stream_nt) {                                                                                 \
+        MG_DISPATCH_R(R, (k_pass<T, RR, 0u, true, M><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, r, z, tab, rb, \
+                                                                          re, done, coarse, ic)));   \
+    } else {                                                                                           \
+        MG_DISPATCH_R(R, (k_pass<T, RR, 0u, false, M><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, r, z, tab, rb, \
+                                                                           re, done, coarse, ic)));  \
+    }
+    if (mode == kPassRestrict) {
+        if (!L.fuse_transfers) return hipErrorInvalidValue;
+        MG_PASS_MODE(1)
+    } else if (mode == kPassProlong) {
+        if (!L.fuse_transfers) return hipErrorInvalidValue;
+        MG_PASS_MODE(2)
+    } else {
+        MG_PASS_MODE(0)
+    }
+#undef MG_PASS_MODE
     return hipGetLastError();
 }
-template hipError_t launch_pass<double>(const mgpcg_problem *, int, int, bool, const double *,
-                                        const double *, double *, const int *, hipStream_t);
-template hipError_t launch_pass<float>(const mgpcg_problem *, int, int, bool, const float *,
-                                       const float *, float *, const int *, hipStream_t);
+template hipError_t launch_pass<double>(const mgpcg_problem *, int, int, int, const double *,
+                                        const double *, double *, const int *, double *, hipStream_t);
+template hipError_t launch_pass<float>(const mgpcg_problem *, int, int, int, const float *,
+                                       const float *, float *, const int *, float *, hipStream_t);
 
 // ------------------------------------------------------------- transfers
 
 // rc = inject(r - A z): only the injection rows of the residual are formed.
 // Threads walk the injection rows in fine order (coalesced operator reads)
 // and scatter into the coarse vector.
-template <typename T, int R>
+template <typename T, int R, bool NT>
 __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restrict__ val,
                                                      const int32_t *__restrict__ col,
                                                      const T *__restrict__ r, const T *__restrict__ z,
@@ -256,14 +411,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restr
     int64_t t = gid / R;
     int v = (int)(gid % R);
     int64_t i = inj_fine[t];
-    T acc = 0;
-#pragma unroll
-    for (int sl = 0; sl < kW; ++sl) {
-        int64_t e = (int64_t)sl * n + i;
-        T a = ld_nt(val + e);
-        int32_t c = ld_nt(col + e);
-        if (a != T(0)) acc = acc + a * z[(int64_t)c * R + v];
-    }
+    T d;
+    const T acc = row_sum<T, R, 0u, NT>(val, col, n, i, z, v, d);
     rc[(int64_t)inj_coarse[t] * R + v] = r[i * R + v] - acc;
 }
 
@@ -273,8 +422,13 @@ hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, cons
     const Level &L = P->lev[level];
     int64_t work = L.n_inj * P->R;
     if (work == 0) return hipSuccess;
-    MG_DISPATCH_R(P->R, (k_restrict<T, RR><<<nblocks(work), kBlock, 0, s>>>(
-                            L.n, val, L.col, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
+    if (L.stream_nt) {
+        MG_DISPATCH_R(P->R, (k_restrict<T, RR, true><<<nblocks(work), kBlock, 0, s>>>(
+                                L.n, val, L.col, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
+    } else {
+        MG_DISPATCH_R(P->R, (k_restrict<T, RR, false><<<nblocks(work), kBlock, 0, s>>>(
+                                L.n, val, L.col, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
+    }
     return hipGetLastError();
 }
 template hipError_t launch_restrict<double>(const mgpcg_problem *, int, const double *, const double *,
@@ -370,71 +524,40 @@ hipError_t launch_theta_grad(const double *lam, const double *x, const double *t
 
 // ----------------------------------------------------- CG with reductions
 //
-// Reduction kernels walk the level-0 reduction table: each workgroup owns a
+// Reduction kernels walk a level-0 reduction table: each workgroup owns a
 // grid-homogeneous segment of rows, and the segments of one grid are
 // consecutive table entries [gb[g], gb[g+1]).  A workgroup reduces its
-// per-rhs partial sums with a fixed wave-shuffle/LDS tree and publishes them;
-// the last workgroup of each grid (ticket counter per grid) then adds that
-// grid's partials in a fixed order and updates the CG scalars of its R
-// systems.  Results are therefore identical from run to run.
+// per-rhs partial sums with a fixed wave-shuffle/LDS tree and stores them.
+// A finalize kernel with one workgroup per grid then adds that grid's
+// partials in a fixed order and updates the CG scalars of its R systems.
+// No atomics: results are identical from run to run, and thousands of
+// workgroups never contend on one counter.
 
 enum Kind { kInit = 0, kRz = 1, kPq = 2, kRr = 3 };
 
-struct RedArgs {
-    const Seg *tab;
-    const int *gb;
-    double *partials;
-    unsigned *tickets;  // this kind's G counters
-    int G;
-};
-
-// Returns true in the last workgroup of grid g; then tot[v] (shared) holds
-// the grid's total for rhs v.  Every thread of the workgroup must call it.
+// wave-shuffle + LDS tree of per-rhs sums; thread v < R gets the total of rhs v
 template <int R>
-__device__ bool reduce_last(double acc, int blk, int g, const RedArgs &ra, double *tot) {
-    __shared__ double sh[(kBlock / 64) * R];
-    __shared__ int is_last;
+__device__ __forceinline__ double block_sum(double acc, double *sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off >= R; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __syncthreads();
     if (lane < R) sh[w * R + lane] = acc;
     __syncthreads();
+    double t = 0.0;
     if (threadIdx.x < R) {
-        double s = sh[threadIdx.x];
-#pragma unroll
-        for (int k = 1; k < kBlock / 64; ++k) s += sh[k * R + threadIdx.x];
-        __hip_atomic_store(&ra.partials[(int64_t)blk * R + threadIdx.x], s, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(&ra.tickets[g], 1u);
-        is_last = (t == (unsigned)(ra.gb[g + 1] - ra.gb[g] - 1));
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    const int v = threadIdx.x % R;
-    double s = 0.0;
-    for (int b = ra.gb[g] + threadIdx.x / R; b < ra.gb[g + 1]; b += kBlock / R)
-        s += __hip_atomic_load(&ra.partials[(int64_t)b * R + v], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-    for (int off = 32; off >= R; off >>= 1) s += __shfl_xor(s, off, 64);
-    __syncthreads();
-    if (lane < R) sh[w * R + lane] = s;
-    __syncthreads();
-    if (threadIdx.x < R) {
-        double t = sh[threadIdx.x];
+        t = sh[threadIdx.x];
 #pragma unroll
         for (int k = 1; k < kBlock / 64; ++k) t += sh[k * R + threadIdx.x];
-        tot[threadIdx.x] = t;
     }
-    if (threadIdx.x == 0)
-        __hip_atomic_store(&ra.tickets[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    return true;
+    return t;
+}
+
+template <int R>
+__device__ __forceinline__ void store_partial(double acc, int blk, double *partials) {
+    __shared__ double sh[(kBlock / 64) * R];
+    const double t = block_sum<R>(acc, sh);
+    if (threadIdx.x < R) partials[(int64_t)blk * R + threadIdx.x] = t;
 }
 
 // all R systems of grid g finished?
@@ -446,39 +569,181 @@ __device__ __forceinline__ bool grid_done(const int *done, int g) {
     return all;
 }
 
-// r = b - A x; ||r|| becomes the reference norm of each system.
+// r = b - A x, partial ||r||^2
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const double *__restrict__ val,
                                                           const int32_t *__restrict__ col,
                                                           const double *__restrict__ b,
                                                           const double *__restrict__ x,
-                                                          double *__restrict__ r, RedArgs ra,
-                                                          Scalars sc) {
-    __shared__ double tot[R];
-    int blk = xcd_remap(blockIdx.x, gridDim.x);
-    Seg e = ra.tab[blk];
+                                                          double *__restrict__ r, const Seg *__restrict__ tab,
+                                                          double *__restrict__ partials) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const Seg e = tab[blk];
+    const int v = threadIdx.x % R, rl = threadIdx.x / R;
+    double acc = 0.0;
+    if (rl < e.count) {
+        const int64_t i = e.row0 + rl;
+        double d;
+        const double s = row_sum<double, R, 0u, true>(val, col, n, i, x, v, d);
+        const double ri = b[i * R + v] - s;
+        r[i * R + v] = ri;
+        acc = ri * ri;
+    }
+    store_partial<R>(acc, blk, partials);
+}
+
+// partial <r, z>
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_dot_rz(const double *__restrict__ r, const double *__restrict__ z,
+                                                   const Seg *__restrict__ tab, double *__restrict__ partials,
+                                                   const int *__restrict__ done) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const Seg e = tab[blk];
+    if (grid_done<R>(done, e.grid)) return;
     const int v = threadIdx.x % R;
     double acc = 0.0;
-    for (int rl = threadIdx.x / R; rl < e.count; rl += kBlock / R) {
-        int64_t i = e.row0 + rl;
-        double s = 0.0;
 #pragma unroll
-        for (int sl = 0; sl < kW; ++sl) {
-            int64_t ei = (int64_t)sl * n + i;
-            double a = ld_nt(val + ei);
-            int32_t c = ld_nt(col + ei);
-            if (a != 0.0) s = s + a * x[(int64_t)c * R + v];
+    for (int u = 0; u < kVecRows; ++u) {
+        const int rl = threadIdx.x / R + u * (kBlock / R);
+        if (rl < e.count) {
+            const int64_t o = (e.row0 + rl) * R + v;
+            acc += r[o] * z[o];
         }
-        double ri = b[i * R + v] - s;
-        r[i * R + v] = ri;
-        acc += ri * ri;
     }
-    if (!reduce_last<R>(acc, blk, e.grid, ra, tot)) return;
-    if (threadIdx.x < R) {
-        int sys = e.grid * R + threadIdx.x;
-        double nr0 = sqrt(tot[threadIdx.x]);
+    store_partial<R>(acc, blk, partials);
+}
+
+// p = z + beta p
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ z, double *__restrict__ p,
+                                                     const Seg *__restrict__ tab, Scalars sc) {
+    const Seg e = tab[xcd_remap(blockIdx.x, gridDim.x)];
+    const int v = threadIdx.x % R;
+    const int sys = e.grid * R + v;
+    if (sc.done[sys]) return;
+    const double beta = sc.beta[sys];
+#pragma unroll
+    for (int u = 0; u < kVecRows; ++u) {
+        const int rl = threadIdx.x / R + u * (kBlock / R);
+        if (rl < e.count) {
+            const int64_t o = (e.row0 + rl) * R + v;
+            p[o] = z[o] + beta * p[o];
+        }
+    }
+}
+
+// q = A p, partial <p, q>
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__restrict__ val,
+                                                    const int32_t *__restrict__ col,
+                                                    const double *__restrict__ p, double *__restrict__ q,
+                                                    const Seg *__restrict__ tab, double *__restrict__ partials,
+                                                    const int *__restrict__ done) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const Seg e = tab[blk];
+    if (grid_done<R>(done, e.grid)) return;
+    const int v = threadIdx.x % R, rl = threadIdx.x / R;
+    double acc = 0.0;
+    if (rl < e.count) {
+        const int64_t i = e.row0 + rl;
+        double d;
+        const double s = row_sum<double, R, 0u, true>(val, col, n, i, p, v, d);
+        q[i * R + v] = s;
+        acc = p[i * R + v] * s;
+    }
+    store_partial<R>(acc, blk, partials);
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, const double *__restrict__ p,
+                                                      double *__restrict__ r, const double *__restrict__ q,
+                                                      const Seg *__restrict__ tab, double *__restrict__ partials,
+                                                      Scalars sc) {
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const Seg e = tab[blk];
+    if (grid_done<R>(sc.done, e.grid)) return;
+    const int v = threadIdx.x % R;
+    const int sys = e.grid * R + v;
+    double acc = 0.0;
+    if (!sc.done[sys]) {
+        const double alpha = sc.alpha[sys];
+#pragma unroll
+        for (int u = 0; u < kVecRows; ++u) {
+            const int rl = threadIdx.x / R + u * (kBlock / R);
+            if (rl < e.count) {
+                const int64_t o = (e.row0 + rl) * R + v;
+                x[o] = x[o] + alpha * p[o];
+                const double ri = r[o] - alpha * q[o];
+                r[o] = ri;
+                acc += ri * ri;
+            }
+        }
+    }
+    store_partial<R>(acc, blk, partials);
+}
+
+// One workgroup per grid: sum the grid's partials in a fixed order, then
+// update the scalars of its R systems.
+//   kInit: nr0 = ||r0||; a zero residual finishes the system with 0 iterations
+//   kRz:   rho = <r,z>; beta = rho/rho_old (0 at the first iteration)
+//   kPq:   alpha = rho/<p,q>, or a breakdown when <p,q> is not finite and > 0
+//   kRr:   record ||r||/||r0|| and test it against tol
+template <int R, int KIND>
+__global__ __launch_bounds__(kBlock) void k_finalize(const int *__restrict__ gb,
+                                                     const double *__restrict__ partials, Scalars sc,
+                                                     double *__restrict__ hist, int hist_cap, double tol) {
+    __shared__ double sh[(kBlock / 64) * R];
+    const int g = blockIdx.x;
+    if (KIND != kInit && grid_done<R>(sc.done, g)) return;
+    const int v = threadIdx.x % R;
+    const int b0 = gb[g], b1 = gb[g + 1];
+    constexpr int kStep = kBlock / R, kU = 8;
+    double s = 0.0;
+    for (int b = b0 + threadIdx.x / R; b < b1; b += kU * kStep) {
+        double t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int bb = b + u * kStep;
+            t[u] = bb < b1 ? partials[(int64_t)bb * R + v] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) s += t[u];
+    }
+    const double tot = block_sum<R>(s, sh);
+    if (threadIdx.x >= R) return;
+    const int sys = g * R + threadIdx.x;
+    if (KIND == kInit) {
+        const double nr0 = sqrt(tot);
         sc.nr0[sys] = nr0;
         if (nr0 == 0.0) {
+            sc.done[sys] = 1;
+            sc.status[sys] = 1;
+            atomicAdd(sc.ndone, 1);
+        }
+        return;
+    }
+    if (sc.done[sys]) return;
+    if (KIND == kRz) {
+        sc.beta[sys] = (sc.iter[sys] == 0) ? 0.0 : tot / sc.rho_old[sys];
+        sc.rho[sys] = tot;
+        sc.rho_old[sys] = tot;
+    } else if (KIND == kPq) {
+        sc.pq[sys] = tot;
+        if (!(tot > 0.0) || !isfinite(tot)) {
+            sc.alpha[sys] = 0.0;
+            sc.status[sys] = MGPCG_ERR_BREAKDOWN;
+            sc.done[sys] = 1;
+            atomicAdd(sc.ndone, 1);
+        } else {
+            sc.alpha[sys] = sc.rho[sys] / tot;
+        }
+    } else {
+        const int k = sc.iter[sys] + 1;
+        sc.iter[sys] = k;
+        const double rel = sqrt(tot) / sc.nr0[sys];
+        if (k <= hist_cap) hist[(int64_t)sys * hist_cap + (k - 1)] = rel;
+        if (tol > 0.0 && rel <= tol) {
             sc.done[sys] = 1;
             sc.status[sys] = 1;
             atomicAdd(sc.ndone, 1);
@@ -486,171 +751,49 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
     }
 }
 
-// rho = <r, z>; beta = rho / rho_old (0 at the first iteration).
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_dot_rz(const double *__restrict__ r,
-                                                   const double *__restrict__ z, RedArgs ra,
-                                                   Scalars sc) {
-    __shared__ double tot[R];
-    int blk = xcd_remap(blockIdx.x, gridDim.x);
-    Seg e = ra.tab[blk];
-    if (grid_done<R>(sc.done, e.grid)) return;
-    const int v = threadIdx.x % R;
-    double acc = 0.0;
-    for (int rl = threadIdx.x / R; rl < e.count; rl += kBlock / R) {
-        int64_t o = (e.row0 + rl) * R + v;
-        acc += r[o] * z[o];
-    }
-    if (!reduce_last<R>(acc, blk, e.grid, ra, tot)) return;
-    if (threadIdx.x < R) {
-        int sys = e.grid * R + threadIdx.x;
-        if (!sc.done[sys]) {
-            double rho = tot[threadIdx.x];
-            sc.beta[sys] = (sc.iter[sys] == 0) ? 0.0 : rho / sc.rho_old[sys];
-            sc.rho[sys] = rho;
-            sc.rho_old[sys] = rho;
-        }
-    }
+template <int KIND>
+static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hist_cap, hipStream_t s) {
+    MG_DISPATCH_R(P->R, (k_finalize<RR, KIND><<<P->G, kBlock, 0, s>>>(P->red_gb[table], P->sc.partials, P->sc,
+                                                                     P->hist, hist_cap, tol)));
+    return hipGetLastError();
 }
 
-// p = z + beta p
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ z, double *__restrict__ p,
-                                                     const Seg *__restrict__ tab, Scalars sc) {
-    Seg e = tab[xcd_remap(blockIdx.x, gridDim.x)];
-    const int v = threadIdx.x % R;
-    const int sys = e.grid * R + v;
-    if (sc.done[sys]) return;
-    const double beta = sc.beta[sys];
-    for (int rl = threadIdx.x / R; rl < e.count; rl += kBlock / R) {
-        int64_t o = (e.row0 + rl) * R + v;
-        p[o] = z[o] + beta * p[o];
-    }
-}
-
-// q = A p; alpha = rho / <p, q>, or a breakdown flag.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__restrict__ val,
-                                                    const int32_t *__restrict__ col,
-                                                    const double *__restrict__ p,
-                                                    double *__restrict__ q, RedArgs ra, Scalars sc) {
-    __shared__ double tot[R];
-    int blk = xcd_remap(blockIdx.x, gridDim.x);
-    Seg e = ra.tab[blk];
-    if (grid_done<R>(sc.done, e.grid)) return;
-    const int v = threadIdx.x % R;
-    double acc = 0.0;
-    for (int rl = threadIdx.x / R; rl < e.count; rl += kBlock / R) {
-        int64_t i = e.row0 + rl;
-        double s = 0.0;
-#pragma unroll
-        for (int sl = 0; sl < kW; ++sl) {
-            int64_t ei = (int64_t)sl * n + i;
-            double a = ld_nt(val + ei);
-            int32_t c = ld_nt(col + ei);
-            if (a != 0.0) s = s + a * p[(int64_t)c * R + v];
-        }
-        q[i * R + v] = s;
-        acc += p[i * R + v] * s;
-    }
-    if (!reduce_last<R>(acc, blk, e.grid, ra, tot)) return;
-    if (threadIdx.x < R) {
-        int sys = e.grid * R + threadIdx.x;
-        if (!sc.done[sys]) {
-            double pq = tot[threadIdx.x];
-            sc.pq[sys] = pq;
-            if (!(pq > 0.0) || !isfinite(pq)) {
-                sc.alpha[sys] = 0.0;
-                sc.status[sys] = MGPCG_ERR_BREAKDOWN;
-                sc.done[sys] = 1;
-                atomicAdd(sc.ndone, 1);
-            } else {
-                sc.alpha[sys] = sc.rho[sys] / pq;
-            }
-        }
-    }
-}
-
-// x += alpha p; r -= alpha q; record ||r|| / ||r0|| and test convergence.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, const double *__restrict__ p,
-                                                      double *__restrict__ r,
-                                                      const double *__restrict__ q, RedArgs ra,
-                                                      Scalars sc, double *__restrict__ hist,
-                                                      int hist_cap, double tol) {
-    __shared__ double tot[R];
-    int blk = xcd_remap(blockIdx.x, gridDim.x);
-    Seg e = ra.tab[blk];
-    if (grid_done<R>(sc.done, e.grid)) return;
-    const int v = threadIdx.x % R;
-    const int sys = e.grid * R + v;
-    const bool live = !sc.done[sys];
-    const double alpha = sc.alpha[sys];
-    double acc = 0.0;
-    if (live) {
-        for (int rl = threadIdx.x / R; rl < e.count; rl += kBlock / R) {
-            int64_t o = (e.row0 + rl) * R + v;
-            x[o] = x[o] + alpha * p[o];
-            double ri = r[o] - alpha * q[o];
-            r[o] = ri;
-            acc += ri * ri;
-        }
-    }
-    if (!reduce_last<R>(acc, blk, e.grid, ra, tot)) return;
-    if (threadIdx.x < R) {
-        int s2 = e.grid * R + threadIdx.x;
-        if (!sc.done[s2]) {
-            int k = sc.iter[s2] + 1;
-            sc.iter[s2] = k;
-            double rel = sqrt(tot[threadIdx.x]) / sc.nr0[s2];
-            if (k <= hist_cap) hist[(int64_t)s2 * hist_cap + (k - 1)] = rel;
-            if (tol > 0.0 && rel <= tol) {
-                sc.done[s2] = 1;
-                sc.status[s2] = 1;
-                atomicAdd(sc.ndone, 1);
-            }
-        }
-    }
-}
-
-static RedArgs red_args(const mgpcg_problem *P, int kind) {
-    RedArgs ra;
-    ra.tab = P->red_tab;
-    ra.gb = P->red_gb;
-    ra.partials = P->sc.partials;
-    ra.tickets = P->sc.tickets + (int64_t)kind * P->G;
-    ra.G = P->G;
-    return ra;
-}
-
+// SpMV-type kernels: one row per thread (table 0); vector kernels: kVecRows
+// rows per thread (table 1).
 hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
-    RedArgs ra = red_args(P, kInit);
-    MG_DISPATCH_R(P->R, (k_init_residual<RR><<<P->n_red, kBlock, 0, s>>>(L.n, L.val64, L.col, P->b,
-                                                                         P->x, P->r, ra, P->sc)));
-    return hipGetLastError();
+    MG_DISPATCH_R(P->R, (k_init_residual<RR><<<P->n_red[0], kBlock, 0, s>>>(
+                            L.n, L.val64, L.col, P->b, P->x, P->r, P->red_tab[0], P->sc.partials)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize<kInit>(P, 0, 0.0, 0, s);
 }
 hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s) {
-    RedArgs ra = red_args(P, kRz);
-    MG_DISPATCH_R(P->R, (k_dot_rz<RR><<<P->n_red, kBlock, 0, s>>>(P->r, P->z, ra, P->sc)));
-    return hipGetLastError();
+    MG_DISPATCH_R(P->R, (k_dot_rz<RR><<<P->n_red[1], kBlock, 0, s>>>(P->r, P->z, P->red_tab[1], P->sc.partials,
+                                                                     P->sc.done)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize<kRz>(P, 1, 0.0, 0, s);
 }
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s) {
-    MG_DISPATCH_R(P->R, (k_update_p<RR><<<P->n_red, kBlock, 0, s>>>(P->z, P->p, P->red_tab, P->sc)));
+    MG_DISPATCH_R(P->R, (k_update_p<RR><<<P->n_red[1], kBlock, 0, s>>>(P->z, P->p, P->red_tab[1], P->sc)));
     return hipGetLastError();
 }
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
-    RedArgs ra = red_args(P, kPq);
-    MG_DISPATCH_R(P->R, (k_spmv_pq<RR><<<P->n_red, kBlock, 0, s>>>(L.n, L.val64, L.col, P->p, P->q,
-                                                                   ra, P->sc)));
-    return hipGetLastError();
+    MG_DISPATCH_R(P->R, (k_spmv_pq<RR><<<P->n_red[0], kBlock, 0, s>>>(L.n, L.val64, L.col, P->p, P->q,
+                                                                      P->red_tab[0], P->sc.partials,
+                                                                      P->sc.done)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize<kPq>(P, 0, 0.0, 0, s);
 }
 hipError_t launch_update_xr(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s) {
-    RedArgs ra = red_args(P, kRr);
-    MG_DISPATCH_R(P->R, (k_update_xr<RR><<<P->n_red, kBlock, 0, s>>>(P->x, P->p, P->r, P->q, ra, P->sc,
-                                                                     P->hist, hist_cap, tol)));
-    return hipGetLastError();
+    MG_DISPATCH_R(P->R, (k_update_xr<RR><<<P->n_red[1], kBlock, 0, s>>>(P->x, P->p, P->r, P->q, P->red_tab[1],
+                                                                        P->sc.partials, P->sc)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize<kRr>(P, 1, tol, hist_cap, s);
 }
 
 }  // namespace mg

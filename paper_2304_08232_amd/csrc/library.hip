@@ -230,6 +230,13 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             Lv.zi_skip[k] = allowed & ((1u << kW) - 1);
             if ((needed & ~allowed) != 0) Lv.zs_ok = false;
         }
+        // the kernels carry the masks of the standard 8-colour numbering as
+        // compile-time constants; any other level clears z and sweeps
+        Lv.zs_std = Lv.zs_ok && Lv.ncol == 8;
+        for (int k = 0; k < Lv.ncol && Lv.zs_std; ++k)
+            if (Lv.zi_skip[k] != standard_zs_mask(k, P->colour_order)) Lv.zs_std = false;
+        const int64_t opbytes = Lv.n * kW * ((P->mg_dtype == MGPCG_FP32 && l > 0 ? 4 : 8) + 4);
+        Lv.stream_nt = opbytes > ((int64_t)64 << 20);
         if (G > 1) {
             std::vector<int32_t> gon(Lv.n);
             for (int g = 0; g < G; ++g)
@@ -265,6 +272,12 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             ci[t] = pairs[t].second;
         }
         F.n_inj = (int64_t)pairs.size();
+        // colour 0 is exactly the injection set, in injection order, and it is
+        // the colour swept last by the backward pass and first by the forward
+        // pass: the restriction and the refinement can ride on those passes
+        F.fuse_transfers = F.ncol > 0 && F.coff[0] == 0 && F.coff[1] == F.n_inj;
+        for (size_t t = 0; t < fi.size() && F.fuse_transfers; ++t)
+            if (fi[t] != (int32_t)t) F.fuse_transfers = false;
         ST_TRY(upload(&F.inj_fine, fi, s));
         ST_TRY(upload(&F.inj_coarse, ci, s));
     }
@@ -292,29 +305,33 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         HIP_TRY(launch_build_ell(P, l, theta, s));
     }
 
-    // level-0 reduction table: grid by grid, chunks of kRedElems/R rows
+    // level-0 reduction tables: grid by grid, chunks of kBlock/R rows (one
+    // per thread) and of kVecRows*kBlock/R rows
     {
         const Level &L0 = P->lev[0];
-        std::vector<Seg> tab;
-        std::vector<int> gb(G + 1, 0);
-        const int rows = kRedElems / R;
-        for (int g = 0; g < G; ++g) {
-            gb[g] = (int)tab.size();
-            const LevelGrid &lg = L0.grids[g];
-            for (int k = 0; k < L0.ncol; ++k)
-                for (int64_t a = 0; a < lg.seg_len[k]; a += rows) {
-                    Seg e;
-                    e.row0 = lg.seg_off[k] + a;
-                    e.count = (int32_t)std::min<int64_t>(rows, lg.seg_len[k] - a);
-                    e.grid = g;
-                    tab.push_back(e);
-                }
+        int64_t max_blocks = 0;
+        for (int t = 0; t < 2; ++t) {
+            std::vector<Seg> tab;
+            std::vector<int> gb(G + 1, 0);
+            const int rows = (t == 0 ? 1 : kVecRows) * kBlock / R;
+            for (int g = 0; g < G; ++g) {
+                gb[g] = (int)tab.size();
+                const LevelGrid &lg = L0.grids[g];
+                for (int k = 0; k < L0.ncol; ++k)
+                    for (int64_t a = 0; a < lg.seg_len[k]; a += rows) {
+                        Seg e;
+                        e.row0 = lg.seg_off[k] + a;
+                        e.count = (int32_t)std::min<int64_t>(rows, lg.seg_len[k] - a);
+                        e.grid = g;
+                        tab.push_back(e);
+                    }
+            }
+            gb[G] = (int)tab.size();
+            P->n_red[t] = (int)tab.size();
+            max_blocks = std::max<int64_t>(max_blocks, (int64_t)tab.size());
+            ST_TRY(upload(&P->red_tab[t], tab, s));
+            ST_TRY(upload(&P->red_gb[t], gb, s));
         }
-        gb[G] = (int)tab.size();
-        P->n_red = (int)tab.size();
-        P->red_gb_host = gb;
-        ST_TRY(upload(&P->red_tab, tab, s));
-        ST_TRY(upload(&P->red_gb, gb, s));
         const int64_t n0 = L0.n * R;
         ST_TRY(dalloc(&P->x, n0));
         ST_TRY(dalloc(&P->r, n0));
@@ -334,9 +351,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(dalloc(&sc.done, S));
         ST_TRY(dalloc(&sc.status, S));
         ST_TRY(dalloc(&sc.ndone, 1));
-        ST_TRY(dalloc(&sc.tickets, (int64_t)kTicketKinds * G));
-        ST_TRY(dalloc(&sc.partials, (int64_t)P->n_red * R));
-        HIP_TRY(launch_fill_u(sc.tickets, (int64_t)kTicketKinds * G, 0u, s));
+        ST_TRY(dalloc(&sc.partials, max_blocks * R));
     }
     HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int), hipHostMallocDefault));
     HIP_TRY(hipStreamSynchronize(s));
@@ -356,11 +371,12 @@ void free_problem(mgpcg_problem *P) {
         dfree(Lv.r); dfree(Lv.z); dfree(Lv.t0); dfree(Lv.t1); dfree(Lv.t2);
     }
     for (auto &p : P->d_natoff) dfree(p);
-    dfree(P->d_dims0); dfree(P->d_natoff0); dfree(P->red_tab); dfree(P->red_gb);
+    dfree(P->d_dims0); dfree(P->d_natoff0);
+    for (int t = 0; t < 2; ++t) { dfree(P->red_tab[t]); dfree(P->red_gb[t]); }
     dfree(P->x); dfree(P->r); dfree(P->z); dfree(P->p); dfree(P->q); dfree(P->b);
     Scalars &sc = P->sc;
     dfree(sc.rho); dfree(sc.rho_old); dfree(sc.alpha); dfree(sc.beta); dfree(sc.nr0); dfree(sc.pq);
-    dfree(sc.iter); dfree(sc.done); dfree(sc.status); dfree(sc.ndone); dfree(sc.tickets);
+    dfree(sc.iter); dfree(sc.done); dfree(sc.status); dfree(sc.ndone);
     dfree(sc.partials);
     dfree(P->hist);
     if (P->pinned_ndone) (void)hipHostFree(P->pinned_ndone);
@@ -372,16 +388,21 @@ void free_problem(mgpcg_problem *P) {
 
 // ----------------------------------------------------------------- drivers
 
-// one symmetric sweep: colours 0..c-1 then c-1..0
+// one symmetric sweep: colours 0..c-1 then c-1..0.  first_mode applies to
+// the first forward pass, last_mode to the last backward pass.
 template <typename T>
-hipError_t sweep(const mgpcg_problem *P, int l, const T *val, const T *r, T *z, bool zero_start,
-                 const int *done, hipStream_t s) {
+hipError_t sweep(const mgpcg_problem *P, int l, const T *val, const T *r, T *z, int first_mode,
+                 int last_mode, T *coarse, const int *done, hipStream_t s) {
     const Level &Lv = P->lev[l];
     hipError_t e;
-    for (int k = 0; k < Lv.ncol; ++k)
-        if ((e = launch_pass<T>(P, l, k, zero_start, val, r, z, done, s)) != hipSuccess) return e;
-    for (int k = Lv.ncol - 1; k >= 0; --k)
-        if ((e = launch_pass<T>(P, l, k, false, val, r, z, done, s)) != hipSuccess) return e;
+    for (int k = 0; k < Lv.ncol; ++k) {
+        const int mode = k == 0 ? first_mode : (first_mode == kPassZeroStart ? kPassZeroStart : kPassPlain);
+        if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s)) != hipSuccess) return e;
+    }
+    for (int k = Lv.ncol - 1; k >= 0; --k) {
+        const int mode = k == 0 ? last_mode : kPassPlain;
+        if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s)) != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -396,25 +417,33 @@ const float *level_val<float>(const mgpcg_problem *P, int l) { return P->lev[l].
 template <typename T>
 hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, hipStream_t s) {
     const int L = P->L;
-    auto rl = [&](int l) -> const T * { return l == 0 ? r0 : (const T *)P->lev[l].r; };
+    auto rl = [&](int l) -> T * { return l == 0 ? const_cast<T *>(r0) : (T *)P->lev[l].r; };
     auto zl = [&](int l) -> T * { return l == 0 ? z0 : (T *)P->lev[l].z; };
     hipError_t e;
     for (int l = 0; l < L; ++l) {
-        const bool zs = P->lev[l].zs_ok;
+        const Level &Lv = P->lev[l];
+        const bool zs = Lv.zs_std && (P->R == 1 || P->R == 16);
         if (!zs) {
-            hipError_t fe = sizeof(T) == 8 ? launch_fill_d((double *)zl(l), P->lev[l].n * P->R, 0.0, s)
-                                           : launch_fill_u((unsigned *)zl(l), P->lev[l].n * P->R, 0u, s);
+            hipError_t fe = sizeof(T) == 8 ? launch_fill_d((double *)zl(l), Lv.n * P->R, 0.0, s)
+                                           : launch_fill_u((unsigned *)zl(l), Lv.n * P->R, 0u, s);
             if (fe != hipSuccess) return fe;
         }
-        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), zs, done, s)) != hipSuccess) return e;
-        if (l + 1 < L &&
-            (e = launch_restrict<T>(P, l, level_val<T>(P, l), rl(l), zl(l), (T *)P->lev[l + 1].r, s)) !=
-                hipSuccess)
+        const bool coarser = l + 1 < L;
+        const bool fuse = coarser && Lv.fuse_transfers;
+        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), zs ? kPassZeroStart : kPassPlain,
+                          fuse ? kPassRestrict : kPassPlain, coarser ? rl(l + 1) : nullptr, done, s)) !=
+            hipSuccess)
+            return e;
+        if (coarser && !fuse &&
+            (e = launch_restrict<T>(P, l, level_val<T>(P, l), rl(l), zl(l), rl(l + 1), s)) != hipSuccess)
             return e;
     }
     for (int l = L - 2; l >= 0; --l) {
-        if ((e = launch_prolong<T>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
-        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), false, done, s)) != hipSuccess) return e;
+        const bool fuse = P->lev[l].fuse_transfers;
+        if (!fuse && (e = launch_prolong<T>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
+        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), fuse ? kPassProlong : kPassPlain, kPassPlain,
+                          zl(l + 1), done, s)) != hipSuccess)
+            return e;
     }
     return hipSuccess;
 }
@@ -700,9 +729,10 @@ mgpcg_status mgpcg_gs_sweep(const mgpcg_problem *p_, int level, const double *r,
     DeviceGuard dg(p->device);
     return with_level_vectors(p, level, r, z, layout, s, true, [&](const void *rv, void *zv) {
         if (p->mg_dtype == MGPCG_FP64)
-            return sweep<double>(p, level, p->lev[level].val64, (const double *)rv, (double *)zv, false,
-                                 nullptr, s);
-        return sweep<float>(p, level, p->lev[level].val32, (const float *)rv, (float *)zv, false, nullptr, s);
+            return sweep<double>(p, level, p->lev[level].val64, (const double *)rv, (double *)zv, kPassPlain,
+                                 kPassPlain, (double *)nullptr, nullptr, s);
+        return sweep<float>(p, level, p->lev[level].val32, (const float *)rv, (float *)zv, kPassPlain, kPassPlain,
+                            (float *)nullptr, nullptr, s);
     });
 }
 
@@ -801,7 +831,6 @@ mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int m
     ST_TRY(in_vec(p, 0, b, p->b, layout, s));
     ST_TRY(in_vec(p, 0, x, p->x, layout, s));
     Scalars &sc = p->sc;
-    HIP_TRY(launch_fill_u(sc.tickets, (int64_t)kTicketKinds * p->G, 0u, s));
     HIP_TRY(launch_fill_i(sc.done, S, 0, s));
     HIP_TRY(launch_fill_i(sc.status, S, 0, s));
     HIP_TRY(launch_fill_i(sc.iter, S, 0, s));

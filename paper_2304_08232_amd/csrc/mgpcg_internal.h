@@ -27,7 +27,7 @@ namespace mg {
 constexpr int kW = 27;        // ELL width (3x3x3 stencil)
 constexpr int kCentre = 13;   // slot of the diagonal
 constexpr int kBlock = 256;   // threads per workgroup
-constexpr int kRedElems = 4096;  // row*rhs elements per reduction block
+constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
 
 // One workgroup's share of rows: [row0, row0+count), all in grid `grid`.
 struct Seg {
@@ -64,6 +64,10 @@ struct Level {
     std::vector<int> pass_first;
     uint32_t zi_skip[8] = {0};  // zero-start forward pass: slots whose neighbour is not yet written
     bool zs_ok = true;          // the zero-start pass is valid for every grid of the level
+    bool zs_std = true;         // ... and its masks are the standard 8-colour ones (compiled in)
+    bool stream_nt = true;      // operator larger than the caches: stream it with non-temporal loads
+    bool fuse_transfers = false;  // colour 0 is exactly the injection set, in injection order, and is
+                                  // swept last by the pre- and first by the post-smoother
 
     // injection to level+1, sorted by fine internal row
     int32_t *inj_fine = nullptr;
@@ -81,10 +85,8 @@ struct Scalars {  // per-system CG state, device arrays of S entries
     double *rho, *rho_old, *alpha, *beta, *nr0, *pq;
     int *iter, *done, *status;
     int *ndone;          // one counter: systems finished
-    unsigned *tickets;   // kTicketKinds * G
     double *partials;    // reduction blocks * R
 };
-constexpr int kTicketKinds = 4;
 
 }  // namespace mg
 
@@ -101,11 +103,12 @@ struct mgpcg_problem {
     int64_t *d_natoff0 = nullptr;  // G+1 natural offsets at level 0
     std::vector<int64_t *> d_natoff;  // per level, G+1
 
-    // level-0 reduction table (grid-homogeneous segments, grouped by grid)
-    mg::Seg *red_tab = nullptr;
-    int n_red = 0;
-    int *red_gb = nullptr;   // G+1: first reduction block of each grid
-    std::vector<int> red_gb_host;
+    // level-0 reduction tables (grid-homogeneous segments, grouped by grid):
+    // [0] one row per thread (SpMV-type CG kernels), [1] kVecRows rows per
+    // thread (vector kernels).  gb: G+1 first table entry of each grid.
+    mg::Seg *red_tab[2] = {nullptr, nullptr};
+    int n_red[2] = {0, 0};
+    int *red_gb[2] = {nullptr, nullptr};
 
     // CG vectors, level 0, internal layout, n0*R doubles
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr;
