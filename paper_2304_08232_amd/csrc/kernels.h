@@ -32,6 +32,10 @@ hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, cons
 template <typename T>
 hipError_t launch_prolong(const mgpcg_problem *P, int level, const T *zc, T *z, hipStream_t s);
 
+// levels coarse_lc..L-1 of one V-cycle in one persistent launch
+hipError_t launch_coarse_vcycle(const mgpcg_problem *P, bool fp32, hipStream_t s);
+int coarse_vcycle_occupancy(int R, bool fp32);  // resident workgroups per CU
+
 hipError_t launch_cast_d2f(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_cast_f2d(const float *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_fill_d(double *p, int64_t n, double v, hipStream_t s);

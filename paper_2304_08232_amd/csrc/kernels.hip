@@ -252,32 +252,14 @@ template hipError_t launch_spmv<float>(const mgpcg_problem *, int, const float *
 //
 // Rows come from the segment table when the problem has several grids;
 // otherwise workgroup b owns rows [row_base + b*rows, ...) of the colour.
+// The update of one (row, rhs) of the pass; shared by the per-pass kernel
+// and the persistent coarse-level kernel.  inj_base is the first row of the
+// colour (the injection rows start there in MODE 1/2).
 template <typename T, int R, uint32_t SKIP, bool NT, int MODE>
-__global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict__ val,
-                                                 const int32_t *__restrict__ col,
-                                                 const T *__restrict__ r, T *z,
-                                                 const Seg *__restrict__ tab, int64_t row_base,
-                                                 int64_t row_end, const int *__restrict__ done,
-                                                 T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    int64_t row0, count;
-    int grid;
-    if (tab) {
-        const Seg e = tab[b];
-        row0 = e.row0;
-        count = e.count;
-        grid = e.grid;
-    } else {
-        row0 = row_base + (int64_t)b * (kBlock / R);
-        count = row_end - row0;
-        grid = 0;
-    }
-    const int rl = threadIdx.x / R, v = threadIdx.x % R;
-    if (rl >= count) return;
-    if (done && done[grid * R + v]) return;
-    const int64_t i = row0 + rl;
+__device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
+                                         const T *__restrict__ r, T *z, int64_t i, int v, int64_t inj_base,
+                                         T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
     const int64_t o = i * R + v;
-
     T a[kW];
     int32_t c[kW];
 #pragma unroll
@@ -290,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict_
     const T rv = r[o];
     T zc = T(0);
     int64_t co = 0;
-    if (MODE != 0) co = (int64_t)inj_coarse[i - row_base] * R + v;
+    if (MODE != 0) co = (int64_t)inj_coarse[i - inj_base] * R + v;
     if (MODE == 2) zc = coarse[co];
     T xv[kW];
 #pragma unroll
@@ -317,6 +299,32 @@ __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict_
             if (a[s] != T(0)) f = f + a[s] * xv[s];
         coarse[co] = rv - f;
     }
+}
+
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE>
+__global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict__ val,
+                                                 const int32_t *__restrict__ col,
+                                                 const T *__restrict__ r, T *z,
+                                                 const Seg *__restrict__ tab, int64_t row_base,
+                                                 int64_t row_end, const int *__restrict__ done,
+                                                 T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t row0, count;
+    int grid;
+    if (tab) {
+        const Seg e = tab[b];
+        row0 = e.row0;
+        count = e.count;
+        grid = e.grid;
+    } else {
+        row0 = row_base + (int64_t)b * (kBlock / R);
+        count = row_end - row0;
+        grid = 0;
+    }
+    const int rl = threadIdx.x / R, v = threadIdx.x % R;
+    if (rl >= count) return;
+    if (done && done[grid * R + v]) return;
+    pass_row<T, R, SKIP, NT, MODE>(n, val, col, r, z, row0 + rl, v, row_base, coarse, inj_coarse);
 }
 
 template <typename T, int R, bool NT>
@@ -392,6 +400,172 @@ template hipError_t launch_pass<double>(const mgpcg_problem *, int, int, int, co
                                         const double *, double *, const int *, double *, hipStream_t);
 template hipError_t launch_pass<float>(const mgpcg_problem *, int, int, int, const float *,
                                        const float *, float *, const int *, float *, hipStream_t);
+
+// --------------------------------------------- persistent coarse V-cycle
+//
+// Levels lc..L-1 of one V-cycle in a single launch.  Every colour pass of a
+// coarse level is small (a few thousand to a few hundred thousand rows), so as
+// separate kernels each costs a launch-and-drain latency floor.  Here the
+// workgroups stay resident and separate the passes with a grid barrier.
+//
+// Barrier: workgroup b publishes the epoch it reached in flags[b]; a barrier
+// completes when every flag has reached the current epoch.  Epochs count up
+// from a device-resident base that the kernel advances itself, so a captured
+// graph can replay the launch unchanged.  Flags and base are cleared by the
+// host before each solve.  Every wait is bounded: on timeout the waiting
+// workgroup raises `err`, every workgroup that sees it stops, and the host
+// reports the error.
+
+__device__ __forceinline__ bool grid_barrier(unsigned *flags, int B, unsigned epoch, int *err,
+                                             long long spin_limit) {
+    __shared__ int s_ok;
+    __threadfence();  // this thread's writes, visible at device scope
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long long spins = 0;
+        int good = 1;
+        for (;;) {
+            int mine = 1;
+            for (int j = threadIdx.x; j < B; j += 64)
+                mine &= __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+            if (__all(mine)) break;
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                good = 0;
+                break;
+            }
+            if (++spins > spin_limit) {
+                if (threadIdx.x == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (threadIdx.x == 0) s_ok = good;
+    }
+    __syncthreads();
+    __threadfence();  // later loads see the other workgroups' writes
+    return s_ok != 0;
+}
+
+template <typename T, int R, uint32_t SKIP, int MODE>
+__device__ __forceinline__ void coarse_phase(const CoarseLevel &lv, int k, T *coarse, int bid, int B) {
+    const int64_t r0 = lv.coff[k], r1 = lv.coff[k + 1];
+    constexpr int rpb = kBlock / R;
+    const int rl = threadIdx.x / R, v = threadIdx.x % R;
+    for (int64_t base = r0 + (int64_t)bid * rpb; base < r1; base += (int64_t)B * rpb) {
+        const int64_t i = base + rl;
+        if (i < r1)
+            pass_row<T, R, SKIP, false, MODE>(lv.n, (const T *)lv.val, lv.col, (const T *)lv.r, (T *)lv.z, i, v,
+                                             r0, coarse, lv.inj_coarse);
+    }
+}
+
+struct CoarseState {
+    unsigned epoch;
+    bool ok;
+    int bid, B;
+};
+
+__device__ __forceinline__ void coarse_sync(const CoarseArgs &A, CoarseState &st) {
+    ++st.epoch;
+    if (st.ok) st.ok = grid_barrier(A.flags, st.B, st.epoch, A.err, A.spin_limit);
+}
+
+// forward zero-start passes K..7 with their compile-time skip masks
+template <typename T, int R, int K>
+__device__ __forceinline__ void coarse_forward_zs(const CoarseArgs &A, const CoarseLevel &lv, CoarseState &st) {
+    if (st.ok) coarse_phase<T, R, zs_mask(K, 0), 0>(lv, K, nullptr, st.bid, st.B);
+    coarse_sync(A, st);
+    if constexpr (K < 7) coarse_forward_zs<T, R, K + 1>(A, lv, st);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_coarse_vcycle(CoarseArgs A) {
+    __shared__ unsigned s_base;
+    CoarseState st;
+    st.B = gridDim.x;
+    st.bid = xcd_remap(blockIdx.x, gridDim.x);
+    if (threadIdx.x == 0) s_base = __hip_atomic_load(A.epoch_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    st.epoch = s_base;
+    st.ok = true;
+    const int L = A.L, lc = A.lc;
+    bool first_sync = true;
+    auto sync = [&]() {
+        coarse_sync(A, st);
+        if (first_sync) {
+            first_sync = false;
+            // every workgroup has read the base by now
+            if (blockIdx.x == 0 && threadIdx.x == 0)
+                __hip_atomic_store(A.epoch_base, s_base + A.nbarriers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    };
+    // down: pre-smoothing, the last backward pass forms the coarse residual
+    for (int l = lc; l < L; ++l) {
+        const CoarseLevel &lv = A.lev[l];
+        if (st.ok) coarse_phase<T, R, zs_mask(0, 0), 0>(lv, 0, nullptr, st.bid, st.B);
+        sync();
+        coarse_forward_zs<T, R, 1>(A, lv, st);
+        for (int k = 7; k >= 1; --k) {
+            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, k, nullptr, st.bid, st.B);
+            sync();
+        }
+        if (l + 1 < L) {
+            if (st.ok) coarse_phase<T, R, 0u, 1>(lv, 0, (T *)A.lev[l + 1].r, st.bid, st.B);
+        } else {
+            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, 0, nullptr, st.bid, st.B);
+        }
+        if (l + 1 < L || lc < L - 1) sync();
+    }
+    // up: the first forward pass applies the refinement, then the sweep
+    for (int l = L - 2; l >= lc; --l) {
+        const CoarseLevel &lv = A.lev[l];
+        if (st.ok) coarse_phase<T, R, 0u, 2>(lv, 0, (T *)A.lev[l + 1].z, st.bid, st.B);
+        sync();
+        for (int k = 1; k < 8; ++k) {
+            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, k, nullptr, st.bid, st.B);
+            sync();
+        }
+        for (int k = 7; k >= 0; --k) {
+            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, k, nullptr, st.bid, st.B);
+            if (!(l == lc && k == 0)) sync();
+        }
+    }
+}
+
+hipError_t launch_coarse_vcycle(const mgpcg_problem *P, bool fp32, hipStream_t s) {
+    CoarseArgs A = P->coarse_args;
+    A.lc = P->coarse_lc;
+    A.L = P->L;
+    for (int l = A.lc; l < P->L; ++l) {
+        const Level &Lv = P->lev[l];
+        A.lev[l].val = fp32 ? (const void *)Lv.val32 : (const void *)Lv.val64;
+    }
+    const int B = P->coarse_blocks;
+    if (P->R == 1) {
+        if (fp32) k_coarse_vcycle<float, 1><<<B, kBlock, 0, s>>>(A);
+        else k_coarse_vcycle<double, 1><<<B, kBlock, 0, s>>>(A);
+    } else if (P->R == 16) {
+        if (fp32) k_coarse_vcycle<float, 16><<<B, kBlock, 0, s>>>(A);
+        else k_coarse_vcycle<double, 16><<<B, kBlock, 0, s>>>(A);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int coarse_vcycle_occupancy(int R, bool fp32) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (R == 1) e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<float, 1>, kBlock, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<double, 1>, kBlock, 0);
+    else if (R == 16)
+        e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<float, 16>, kBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<double, 16>, kBlock, 0);
+    return e == hipSuccess ? nb : 0;
+}
 
 // ------------------------------------------------------------- transfers
 

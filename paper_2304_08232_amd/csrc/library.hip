@@ -353,6 +353,52 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(dalloc(&sc.ndone, 1));
         ST_TRY(dalloc(&sc.partials, max_blocks * R));
     }
+    // persistent coarse-level V-cycle: canonical colour order, standard
+    // 8-colour masks on every coarse level, refinement/restriction fused on
+    // the coarse levels that have a coarser one
+    {
+        bool ok = L >= 2 && P->colour_order == 0 && (R == 1 || R == 16);
+        for (int l = 1; l < L && ok; ++l) ok = P->lev[l].zs_std && P->lev[l].ncol == 8;
+        for (int l = 1; l + 1 < L && ok; ++l) ok = P->lev[l].fuse_transfers;
+        const bool fp32 = P->mg_dtype == MGPCG_FP32;
+        int ncu = 0;
+        if (ok && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess) ok = false;
+        const int occ = ok ? coarse_vcycle_occupancy(R, fp32) : 0;
+        if (ok && occ < 1) ok = false;
+        if (ok) {
+            const int lc = 1;
+            int64_t maxrows = 0;
+            const Level &Lc = P->lev[lc];
+            for (int k = 0; k < Lc.ncol; ++k) maxrows = std::max<int64_t>(maxrows, Lc.coff[k + 1] - Lc.coff[k]);
+            const int64_t want = (maxrows + kBlock / R - 1) / (kBlock / R);
+            const int B = (int)std::max<int64_t>(1, std::min<int64_t>(want, ncu));
+            P->coarse_lc = lc;
+            P->coarse_blocks = B;
+            CoarseArgs &A = P->coarse_args;
+            memset(&A, 0, sizeof(A));
+            for (int l = lc; l < L; ++l) {
+                const Level &Lv = P->lev[l];
+                CoarseLevel &cl = A.lev[l];
+                cl.n = Lv.n;
+                cl.col = Lv.col;
+                cl.r = Lv.r;
+                cl.z = Lv.z;
+                cl.inj_coarse = Lv.inj_coarse;
+                for (int k = 0; k <= 8; ++k) cl.coff[k] = Lv.coff[std::min(k, Lv.ncol)];
+            }
+            const int phases = 16 * (L - lc) + 16 * (L - 1 - lc);
+            A.nbarriers = (unsigned)(phases - 1);
+            ST_TRY(dalloc(&P->coarse_flags, (int64_t)B + 1));
+            ST_TRY(dalloc(&P->coarse_err, 1));
+            A.flags = P->coarse_flags;
+            A.epoch_base = P->coarse_flags + B;
+            A.err = P->coarse_err;
+            A.spin_limit = 1ll << 21;
+            HIP_TRY(launch_fill_u(P->coarse_flags, (int64_t)B + 1, 0u, s));
+            HIP_TRY(launch_fill_i(P->coarse_err, 1, 0, s));
+        }
+        P->coarse_ok = ok;
+    }
     HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int), hipHostMallocDefault));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
@@ -379,6 +425,8 @@ void free_problem(mgpcg_problem *P) {
     dfree(sc.iter); dfree(sc.done); dfree(sc.status); dfree(sc.ndone);
     dfree(sc.partials);
     dfree(P->hist);
+    dfree(P->coarse_flags);
+    dfree(P->coarse_err);
     if (P->pinned_ndone) (void)hipHostFree(P->pinned_ndone);
     if (P->iter_graph) (void)hipGraphExecDestroy(P->iter_graph);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
@@ -413,10 +461,13 @@ const double *level_val<double>(const mgpcg_problem *P, int l) { return P->lev[l
 template <>
 const float *level_val<float>(const mgpcg_problem *P, int l) { return P->lev[l].val32; }
 
-// Listing 1: z0 = MG(0, r0); every level starts from z = 0.
+// Listing 1: z0 = MG(0, r0); every level starts from z = 0.  With the
+// persistent coarse kernel, levels coarse_lc..L-1 run in one launch between
+// the level-0 pre- and post-smoothers.
 template <typename T>
 hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, hipStream_t s) {
-    const int L = P->L;
+    const bool persistent = P->coarse_ok && P->coarse_mode == 1;
+    const int L = persistent ? P->coarse_lc : P->L;
     auto rl = [&](int l) -> T * { return l == 0 ? const_cast<T *>(r0) : (T *)P->lev[l].r; };
     auto zl = [&](int l) -> T * { return l == 0 ? z0 : (T *)P->lev[l].z; };
     hipError_t e;
@@ -428,7 +479,7 @@ hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, h
                                            : launch_fill_u((unsigned *)zl(l), Lv.n * P->R, 0u, s);
             if (fe != hipSuccess) return fe;
         }
-        const bool coarser = l + 1 < L;
+        const bool coarser = l + 1 < P->L;
         const bool fuse = coarser && Lv.fuse_transfers;
         if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), zs ? kPassZeroStart : kPassPlain,
                           fuse ? kPassRestrict : kPassPlain, coarser ? rl(l + 1) : nullptr, done, s)) !=
@@ -438,7 +489,8 @@ hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, h
             (e = launch_restrict<T>(P, l, level_val<T>(P, l), rl(l), zl(l), rl(l + 1), s)) != hipSuccess)
             return e;
     }
-    for (int l = L - 2; l >= 0; --l) {
+    if (persistent && (e = launch_coarse_vcycle(P, sizeof(T) == 4, s)) != hipSuccess) return e;
+    for (int l = (persistent ? L - 1 : L - 2); l >= 0; --l) {
         const bool fuse = P->lev[l].fuse_transfers;
         if (!fuse && (e = launch_prolong<T>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
         if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), fuse ? kPassProlong : kPassPlain, kPassPlain,
@@ -519,9 +571,28 @@ mgpcg_status out_vec(const mgpcg_problem *P, int l, const double *src, double *d
     return MGPCG_OK;
 }
 
+// clear the persistent kernel's barrier flags, epoch base and error flag
+mgpcg_status reset_coarse(mgpcg_problem *P, hipStream_t s) {
+    if (!P->coarse_ok) return MGPCG_OK;
+    HIP_TRY(launch_fill_u(P->coarse_flags, (int64_t)P->coarse_blocks + 1, 0u, s));
+    HIP_TRY(launch_fill_i(P->coarse_err, 1, 0, s));
+    return MGPCG_OK;
+}
+
+// synchronises; reports a device-side failure of the coarse-level kernel
+mgpcg_status device_error(mgpcg_problem *P, hipStream_t s) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!P->coarse_ok) return MGPCG_OK;
+    int err = 0;
+    HIP_TRY(hipMemcpy(&err, P->coarse_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) return fail(MGPCG_ERR_HIP, "a grid barrier of the coarse-level kernel timed out");
+    return MGPCG_OK;
+}
+
 mgpcg_status fetch_result(mgpcg_problem *P, int max_iters, double *history_host, int *iters_host,
                           hipStream_t s) {
     const int S = P->S;
+    ST_TRY(device_error(P, s));
     std::vector<int> iters(S), status(S);
     HIP_TRY(hipMemcpyAsync(iters.data(), P->sc.iter, S * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(status.data(), P->sc.status, S * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -792,6 +863,7 @@ mgpcg_status mgpcg_mg_vcycle(const mgpcg_problem *p_, const double *r, double *z
     if (!r || !z) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
     mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
     DeviceGuard dg(p->device);
+    ST_TRY(reset_coarse(p, s));
     return with_level_vectors(p, 0, r, z, layout, s, false, [&](const void *rv, void *zv) {
         if (p->mg_dtype == MGPCG_FP64) return vcycle<double>(p, (const double *)rv, (double *)zv, nullptr, s);
         return vcycle<float>(p, (const float *)rv, (float *)zv, nullptr, s);
@@ -831,6 +903,7 @@ mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int m
     ST_TRY(in_vec(p, 0, b, p->b, layout, s));
     ST_TRY(in_vec(p, 0, x, p->x, layout, s));
     Scalars &sc = p->sc;
+    ST_TRY(reset_coarse(p, s));
     HIP_TRY(launch_fill_i(sc.done, S, 0, s));
     HIP_TRY(launch_fill_i(sc.status, S, 0, s));
     HIP_TRY(launch_fill_i(sc.iter, S, 0, s));
@@ -897,6 +970,23 @@ mgpcg_status mgpcg_set_graph_mode(mgpcg_problem *p, int on) {
         p->iter_graph = nullptr;
     }
     return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_set_coarse_mode(mgpcg_problem *p, int mode) {
+    ST_TRY(check_problem(p));
+    if (mode != 0 && mode != 1) return fail(MGPCG_ERR_INVALID_ARG, "coarse mode must be 0 or 1");
+    p->coarse_mode = mode;
+    if (p->iter_graph) {
+        (void)hipGraphExecDestroy(p->iter_graph);
+        p->iter_graph = nullptr;
+    }
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_check(mgpcg_problem *p, hipStream_t stream) {
+    ST_TRY(check_problem(p));
+    DeviceGuard dg(p->device);
+    return device_error(p, stream);
 }
 
 }  // extern "C"

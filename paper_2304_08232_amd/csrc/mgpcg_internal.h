@@ -81,6 +81,25 @@ struct Level {
     double *t0 = nullptr, *t1 = nullptr, *t2 = nullptr;
 };
 
+// device view of one level for the persistent coarse-level kernel
+struct CoarseLevel {
+    int64_t n;
+    const void *val;
+    const int32_t *col;
+    void *r, *z;
+    const int32_t *inj_coarse;  // to level+1, indexed by row - coff[0]
+    int64_t coff[9];
+};
+struct CoarseArgs {
+    CoarseLevel lev[MGPCG_MAX_LEVELS];
+    int lc, L;
+    unsigned nbarriers;
+    unsigned *flags;       // one per workgroup
+    unsigned *epoch_base;  // advanced by the kernel at each launch
+    int *err;              // set when a barrier wait times out
+    long long spin_limit;
+};
+
 struct Scalars {  // per-system CG state, device arrays of S entries
     double *rho, *rho_old, *alpha, *beta, *nr0, *pq;
     int *iter, *done, *status;
@@ -119,6 +138,15 @@ struct mgpcg_problem {
     double last_tol = 0.0;
 
     int *pinned_ndone = nullptr;  // host-pinned mirror for convergence checks
+
+    // persistent coarse-level V-cycle (levels coarse_lc..L-1 in one launch)
+    bool coarse_ok = false;   // supported for this problem
+    int coarse_mode = 1;      // 1: use it when supported; 0: one kernel per pass
+    int coarse_lc = 1;
+    int coarse_blocks = 0;
+    mg::CoarseArgs coarse_args{};
+    unsigned *coarse_flags = nullptr;   // coarse_blocks + 1 (last: epoch base)
+    int *coarse_err = nullptr;
 
     // captured iteration graph
     hipStream_t cap_stream = nullptr;

@@ -25,7 +25,8 @@ ABI_FUNCTIONS = [
     "mgpcg_create", "mgpcg_destroy", "mgpcg_info", "mgpcg_set_theta", "mgpcg_to_internal",
     "mgpcg_to_natural", "mgpcg_spmv", "mgpcg_make_rhs_ones", "mgpcg_gs_sweep", "mgpcg_restrict",
     "mgpcg_prolong_add", "mgpcg_mg_vcycle", "mgpcg_pcg_solve", "mgpcg_solve_result",
-    "mgpcg_theta_grad", "mgpcg_set_graph_mode", "mgpcg_last_error",
+    "mgpcg_theta_grad", "mgpcg_set_graph_mode", "mgpcg_set_coarse_mode", "mgpcg_check",
+    "mgpcg_last_error",
 ]
 
 
@@ -73,6 +74,8 @@ def lib():
         L.mgpcg_solve_result.argtypes = [vp, i32, vp, vp, vp]
         L.mgpcg_theta_grad.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mgpcg_set_graph_mode.argtypes = [vp, i32]
+        L.mgpcg_set_coarse_mode.argtypes = [vp, i32]
+        L.mgpcg_check.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -181,6 +184,14 @@ def mgpcg_theta_grad(h, lam, x, theta, grad, stream=None):
 
 def mgpcg_set_graph_mode(h, on):
     return _check(lib().mgpcg_set_graph_mode(C.c_void_p(h), int(on)))
+
+
+def mgpcg_set_coarse_mode(h, mode):
+    return _check(lib().mgpcg_set_coarse_mode(C.c_void_p(h), int(mode)))
+
+
+def mgpcg_check(h, stream=None):
+    return _check(lib().mgpcg_check(C.c_void_p(h), _stream(stream)))
 
 
 # ------------------------------------------------------------- convenience
@@ -293,6 +304,12 @@ class Problem:
 
     def set_graph_mode(self, on):
         mgpcg_set_graph_mode(self.h, on)
+
+    def set_coarse_mode(self, mode):
+        mgpcg_set_coarse_mode(self.h, mode)
+
+    def check(self):
+        return mgpcg_check(self.h)
 
 
 class MGPCGSolve(torch.autograd.Function):

@@ -324,3 +324,53 @@ def test_128cubed_pcg_history_golden(mg, p128):
     idx = np.array(gold["sample_index"])
     np.testing.assert_allclose(xg[idx], np.array(gold["sample_x"]), rtol=1e-12, atol=0)
     assert abs(np.abs(xg - 1.0).max() - gold["max_abs_err"]) <= 1e-12
+
+
+# ------------------------------------------- coarse levels: persistent kernel
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (24, 16, 32)])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_coarse_persistent_equals_per_pass(mg, dims, dtype):
+    o = Oracle(*dims)
+    p = mg.Problem(dims, mg_dtype=dtype)
+    r = dev(inputs.uniform(60, o.n()))
+    outs = []
+    for mode in (0, 1, 0, 1):
+        p.set_coarse_mode(mode)
+        z = p.vcycle(r)
+        assert p.check() == mg.OK
+        outs.append(host(z))
+    for z in outs[1:]:
+        np.testing.assert_array_equal(z, outs[0])
+    ref = o.vcycle(host(r)) if dtype == "fp64" else o.vcycle32(host(r))
+    np.testing.assert_array_equal(outs[1], ref)
+    b = p.make_rhs_ones()
+    hs = []
+    for mode in (1, 0):
+        p.set_coarse_mode(mode)
+        x, h, its, st = p.solve(b, max_iters=30)
+        assert st == mg.OK
+        hs.append((host(x), h.copy()))
+    np.testing.assert_array_equal(hs[0][0], hs[1][0])
+    np.testing.assert_array_equal(hs[0][1], hs[1][1])
+
+
+def test_coarse_persistent_batched_and_multi_rhs(mg):
+    dims = [(16, 16, 16), (24, 16, 32), (8, 16, 8)]
+    p = mg.Problem(dims)
+    sizes = [a * b * c for a, b, c in dims]
+    r = dev(inputs.batch_rhs(61, sizes))
+    p.set_coarse_mode(0)
+    z0 = host(p.vcycle(r))
+    p.set_coarse_mode(1)
+    z1 = host(p.vcycle(r))
+    assert p.check() == mg.OK
+    np.testing.assert_array_equal(z0, z1)
+    pm = mg.Problem((16, 16, 16), nrhs=16)
+    B = dev(inputs.multi_rhs(62, 16, 4096))
+    pm.set_coarse_mode(0)
+    z0 = host(pm.vcycle(B))
+    pm.set_coarse_mode(1)
+    z1 = host(pm.vcycle(B))
+    assert pm.check() == mg.OK
+    np.testing.assert_array_equal(z0, z1)
