@@ -419,11 +419,14 @@ template hipError_t launch_pass<float>(const mgpcg_problem *, int, int, int, con
 __device__ __forceinline__ bool grid_barrier(unsigned *flags, int B, unsigned epoch, int *err,
                                              long long spin_limit) {
     __shared__ int s_ok;
-    __threadfence();  // this thread's writes, visible at device scope
+    // the workgroup barrier waits until every wave's stores have reached its
+    // L2; one release fence then writes that L2 back for the other XCDs
     __syncthreads();
     if (threadIdx.x < 64) {
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         long long spins = 0;
         int good = 1;
         for (;;) {
@@ -440,12 +443,13 @@ __device__ __forceinline__ bool grid_barrier(unsigned *flags, int B, unsigned ep
                 good = 0;
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
         }
+        // acquire: the CU's caches and this XCD's L2 drop stale lines
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (threadIdx.x == 0) s_ok = good;
     }
     __syncthreads();
-    __threadfence();  // later loads see the other workgroups' writes
     return s_ok != 0;
 }
 

@@ -2,6 +2,7 @@
 // iteration graph capture, and the C ABI declared in mgpcg.h.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -236,7 +237,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         for (int k = 0; k < Lv.ncol && Lv.zs_std; ++k)
             if (Lv.zi_skip[k] != standard_zs_mask(k, P->colour_order)) Lv.zs_std = false;
         const int64_t opbytes = Lv.n * kW * ((P->mg_dtype == MGPCG_FP32 && l > 0 ? 4 : 8) + 4);
-        Lv.stream_nt = opbytes > ((int64_t)64 << 20);
+        int64_t nt_bytes = (int64_t)128 << 20;  // operators above half the Infinity Cache are streamed
+        if (const char *env = getenv("MGPCG_NT_BYTES")) nt_bytes = atoll(env);  // tuning override
+        Lv.stream_nt = opbytes > nt_bytes;
         if (G > 1) {
             std::vector<int32_t> gon(Lv.n);
             for (int g = 0; g < G; ++g)
@@ -371,7 +374,11 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             const Level &Lc = P->lev[lc];
             for (int k = 0; k < Lc.ncol; ++k) maxrows = std::max<int64_t>(maxrows, Lc.coff[k + 1] - Lc.coff[k]);
             const int64_t want = (maxrows + kBlock / R - 1) / (kBlock / R);
-            const int B = (int)std::max<int64_t>(1, std::min<int64_t>(want, ncu));
+            int B = (int)std::max<int64_t>(1, std::min<int64_t>(want, ncu));
+            if (const char *env = getenv("MGPCG_COARSE_BLOCKS")) {  // tuning override
+                const int b = atoi(env);
+                if (b >= 1 && b <= ncu) B = b;
+            }
             P->coarse_lc = lc;
             P->coarse_blocks = B;
             CoarseArgs &A = P->coarse_args;

@@ -141,7 +141,7 @@ struct mgpcg_problem {
 
     // persistent coarse-level V-cycle (levels coarse_lc..L-1 in one launch)
     bool coarse_ok = false;   // supported for this problem
-    int coarse_mode = 1;      // 1: use it when supported; 0: one kernel per pass
+    int coarse_mode = 0;      // 1: use it when supported; 0: one kernel per pass (default: faster here)
     int coarse_lc = 1;
     int coarse_blocks = 0;
     mg::CoarseArgs coarse_args{};
