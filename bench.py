@@ -235,6 +235,17 @@ def main():
     its = np.zeros(1, np.int32)
     st = mg.mgpcg_solve_result(prob.h, ITERS, hist, its)
     log(f"solve: {t_step * 1e3:.3f} ms per 50 iterations, relres[50] = {hist[-1]:.6e}, status {st}")
+    # practical ceiling: a plain device copy of 1 GiB (torch), read + write bytes
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (time.perf_counter() - t0) / 1e9
+    del src, dst
     B, F = perfmodel.iteration([GRID], LEVELS, "fp64")
     gflops = F * ITERS / time_to_solve / 1e9
     hbm_frac = B * ITERS / time_to_solve / (perfmodel.HBM_PEAK_GBS * 1e9)
@@ -250,6 +261,7 @@ def main():
         "nominal_hbm_frac": round(hbm_frac, 4),
         "us_per_iteration": round(t_step / ITERS * 1e6, 2),
         "final_relres": float(hist[-1]),
+        "stream_copy_gbs": round(copy_gbs, 1),
         "roofline": {"bound": "hbm", "kernel": "k_pass<double,1,false> (level-0 colour pass)",
                      "achieved": round(achieved, 1), "peak": perfmodel.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / perfmodel.HBM_PEAK_GBS, 4),
