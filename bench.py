@@ -201,6 +201,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--coarse-mode", type=int, default=0,
+                    help="0: one kernel per coarse colour pass; 1: persistent coarse V-cycle")
     ap.add_argument("--only-kernel", action="store_true",
                     help="time only the dominant kernel (for counter runs)")
     args = ap.parse_args()
@@ -215,6 +217,7 @@ def main():
 
     torch.cuda.set_device(0)
     prob = mg.Problem(GRID, levels=LEVELS)
+    prob.set_coarse_mode(args.coarse_mode)
     log(f"setup done: n={prob.n(0)} nnz={prob.nnz(0)}")
     per_launch_bytes = perfmodel.sweep_pass_bytes(GRID)
     t_launch, launches = dominant_kernel(torch, mg, prob)
@@ -256,6 +259,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "fp64_mgpcg_128cubed_50it", "grid": list(GRID), "levels": LEVELS,
+                   "coarse_mode": args.coarse_mode,
                    "iterations_per_step": ITERS, "colour_order": 0, "rhs": "A*ones", "x0": "zeros",
                    "layout": "internal (resident in HBM)"},
         "nominal_hbm_frac": round(hbm_frac, 4),

@@ -176,11 +176,12 @@ mgpcg_status mgpcg_theta_grad(const mgpcg_problem *p, const double *lambda, cons
  * iteration's kernels one by one.  Results are identical either way. */
 mgpcg_status mgpcg_set_graph_mode(mgpcg_problem *p, int on);
 
-/* Execution of the coarse levels of the V-cycle: mode 1 (default) runs
- * levels 1..L-1 of each V-cycle in one persistent launch whose workgroups
- * separate the colour passes with a grid barrier (used when the colour order
- * is 0, nrhs is 1 or 16, and every coarse grid has extents >= 2); mode 0
- * launches one kernel per colour pass.  Results are identical either way. */
+/* Execution of the coarse levels of the V-cycle: mode 0 (default) launches
+ * one kernel per colour pass; mode 1 runs levels 1..L-1 of each V-cycle in
+ * one persistent launch whose workgroups separate the phases with a grid
+ * barrier (used when nrhs is 1 and every coarse grid has the standard
+ * 8-colour numbering; otherwise mode 0 runs).  Results are identical either
+ * way. */
 mgpcg_status mgpcg_set_coarse_mode(mgpcg_problem *p, int mode);
 
 /* Synchronises the stream and reports a device-side failure of earlier

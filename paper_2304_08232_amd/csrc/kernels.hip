@@ -52,6 +52,18 @@ __device__ __forceinline__ int find_grid(const int64_t *off, int G, int64_t q) {
 
 inline int nblocks(int64_t work) { return (int)((work + kBlock - 1) / kBlock); }
 
+// colour row ranges of a level, passed by value
+struct CoffTable {
+    int64_t coff[9];
+    int ncol;
+};
+inline CoffTable coff_table(const Level &L) {
+    CoffTable t;
+    t.ncol = L.ncol;
+    for (int k = 0; k <= 8; ++k) t.coff[k] = L.coff[k < L.ncol ? k : L.ncol];
+    return t;
+}
+
 // Load helper: streaming (non-temporal) loads for operators far larger than
 // the caches, ordinary loads otherwise so that coarse operators stay resident.
 template <bool NT, typename T>
@@ -60,30 +72,50 @@ __device__ __forceinline__ T ld(const T *p) {
     else return *p;
 }
 
+// The 27 column bases of one colour, passed by value in the kernel arguments
+// of a colour pass (no separate load of the base table).
+struct Base27 {
+    int32_t v[27];
+    __device__ __forceinline__ int32_t operator[](int s) const { return v[s]; }
+};
+
+// Operator values a[s] and gathered x values xv[s] of the 27 slots of row i
+// (0 for padding slots and for slots in the compile-time SKIP mask).  All
+// value and column (or column-delta) loads of the row are issued first, then
+// the dependent gathers, so a wave keeps 54 streaming loads and then 27
+// gathers in flight.
+template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
+__device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_t *__restrict__ col,
+                                         const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
+                                         const T *x, int v, T (&a)[kW], T (&xv)[kW]) {
+    int32_t c[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
+        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb[s] + (int32_t)ld<NT>(dcol + (int64_t)s * n + i));
+        else c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
+    }
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        xv[s] = (!sk && a[s] != T(0)) ? x[(int64_t)c[s] * R + v] : T(0);
+    }
+}
+
 // sum_j a_ij x_j over the 27 slots of row i, in slot order (ascending natural
 // column order), skipping padding slots (value 0).  All value and column
 // loads of the row are issued before the dependent gathers, so a wave keeps
 // 54 streaming loads and then 27 gathers in flight.  Slots whose bit is set
 // in the compile-time SKIP mask are left out entirely (their x is known to be
 // zero); the diagonal value is always loaded and returned in d.
-template <typename T, int R, uint32_t SKIP, bool NT>
-__device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *__restrict__ col, int64_t n,
+template <typename T, int R, uint32_t SKIP, bool NT, bool D8>
+__device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *__restrict__ col,
+                                     const int8_t *__restrict__ dcol, const int32_t *__restrict__ sb, int64_t n,
                                      int64_t i, const T *x, int v, T &d) {
-    T a[kW];
-    int32_t c[kW];
-#pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
-        c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
-    }
+    T a[kW], xv[kW];
+    load_row<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, x, v, a, xv);
     d = a[kCentre];
-    T xv[kW];
-#pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        xv[s] = (!sk && a[s] != T(0)) ? x[(int64_t)c[s] * R + v] : T(0);
-    }
     T acc = 0;
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
@@ -91,6 +123,13 @@ __device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *_
         if (!sk && a[s] != T(0)) acc = acc + a[s] * xv[s];
     }
     return acc;
+}
+
+// colour of row i from the colour ranges (at most 8)
+__device__ __forceinline__ int colour_of(const int64_t *coff, int ncol, int64_t i) {
+    int k = 0;
+    while (k + 1 < ncol && i >= coff[k + 1]) ++k;
+    return k;
 }
 
 // Zero-start skip mask of colour k for the standard colouring of grids whose
@@ -146,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_build_ell(
         int64_t e = (int64_t)s * n + i;
         if (val64) val64[e] = v;
         if (val32) val32[e] = (float)v;
-        col[e] = c;
+        if (col) col[e] = c;
     }
 }
 
@@ -156,6 +195,39 @@ hipError_t launch_build_ell(const mgpcg_problem *P, int level, const double *the
     k_build_ell<<<nblocks(L.n), kBlock, 0, s>>>(L.n, P->G, L.iperm, L.perm, P->d_natoff[level],
                                                 P->d_dims0, level, P->d_natoff0, theta, L.val64,
                                                 L.val32, L.col);
+    return hipGetLastError();
+}
+
+// Delta-code the columns of one (single-grid) level: dcol = col - i - base,
+// for real entries only; `bad` is set when some delta does not fit in int8.
+__global__ __launch_bounds__(kBlock) void k_delta_encode(int64_t n, const double *__restrict__ val64,
+                                                         const float *__restrict__ val32,
+                                                         const int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ base,
+                                                         const int64_t *__restrict__ coff, int ncol,
+                                                         int8_t *__restrict__ dcol, int *__restrict__ bad) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int k = colour_of(coff, ncol, i);
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const int64_t e = (int64_t)s * n + i;
+        const bool real = val64 ? val64[e] != 0.0 : val32[e] != 0.0f;
+        int64_t dlt = real ? (int64_t)col[e] - i - base[k * kW + s] : 0;
+        if (dlt < -128 || dlt > 127) {
+            atomicOr(bad, 1);
+            dlt = 0;
+        }
+        dcol[e] = (int8_t)dlt;
+    }
+}
+
+hipError_t launch_delta_encode(const mgpcg_problem *P, int level, const int64_t *coff_dev, int *bad,
+                               hipStream_t s) {
+    const Level &L = P->lev[level];
+    if (L.n == 0) return hipSuccess;
+    k_delta_encode<<<nblocks(L.n), kBlock, 0, s>>>(L.n, L.val64, L.val32, L.col, L.dbase, coff_dev, L.ncol,
+                                                   L.dcol, bad);
     return hipGetLastError();
 }
 
@@ -206,16 +278,18 @@ hipError_t launch_permute(const mgpcg_problem *P, int level, const double *src, 
 
 // y = A x over all rows; one thread per (row, rhs).  The R lanes of a row
 // load the same operator entry (one transaction) and R consecutive x values.
-template <typename T, int R>
+template <typename T, int R, bool D8>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const T *__restrict__ val,
-                                                 const int32_t *__restrict__ col,
+                                                 const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
+                                                 const int32_t *__restrict__ dbase, CoffTable ct,
                                                  const T *__restrict__ x, T *__restrict__ y) {
     int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (gid >= n * R) return;
     int64_t i = gid / R;
     int v = (int)(gid % R);
+    const int32_t *sb = D8 ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
     T d;
-    y[gid] = row_sum<T, R, 0u, true>(val, col, n, i, x, v, d);
+    y[gid] = row_sum<T, R, 0u, true, D8>(val, col, dcol, sb, n, i, x, v, d);
 }
 
 template <typename T>
@@ -223,7 +297,14 @@ hipError_t launch_spmv(const mgpcg_problem *P, int level, const T *val, const T 
     const Level &L = P->lev[level];
     int64_t work = L.n * P->R;
     if (work == 0) return hipSuccess;
-    MG_DISPATCH_R(P->R, (k_spmv<T, RR><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, x, y)));
+    const CoffTable ct = coff_table(L);
+    if (L.dcol) {
+        MG_DISPATCH_R(P->R, (k_spmv<T, RR, true><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol, L.dbase,
+                                                                               ct, x, y)));
+    } else {
+        MG_DISPATCH_R(P->R, (k_spmv<T, RR, false><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol,
+                                                                                L.dbase, ct, x, y)));
+    }
     return hipGetLastError();
 }
 template hipError_t launch_spmv<double>(const mgpcg_problem *, int, const double *, const double *,
@@ -255,31 +336,20 @@ template hipError_t launch_spmv<float>(const mgpcg_problem *, int, const float *
 // The update of one (row, rhs) of the pass; shared by the per-pass kernel
 // and the persistent coarse-level kernel.  inj_base is the first row of the
 // colour (the injection rows start there in MODE 1/2).
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE>
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, class SB>
 __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
+                                         const int8_t *__restrict__ dcol, const SB &sb,
                                          const T *__restrict__ r, T *z, int64_t i, int v, int64_t inj_base,
                                          T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
     const int64_t o = i * R + v;
-    T a[kW];
-    int32_t c[kW];
-#pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
-        c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
-    }
-    const T d = a[kCentre];
     const T rv = r[o];
     T zc = T(0);
     int64_t co = 0;
     if (MODE != 0) co = (int64_t)inj_coarse[i - inj_base] * R + v;
     if (MODE == 2) zc = coarse[co];
-    T xv[kW];
-#pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        xv[s] = (!sk && a[s] != T(0)) ? z[(int64_t)c[s] * R + v] : T(0);
-    }
+    T a[kW], xv[kW];
+    load_row<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, z, v, a, xv);
+    const T d = a[kCentre];
     // z_i before this pass (refined in MODE 2); 0 on a zero start
     const T zi = SKIP ? T(0) : (MODE == 2 ? xv[kCentre] + zc : xv[kCentre]);
     if (MODE == 2) xv[kCentre] = zi;
@@ -301,9 +371,10 @@ __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, c
     }
 }
 
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE>
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8>
 __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict__ val,
-                                                 const int32_t *__restrict__ col,
+                                                 const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
+                                                 const Base27 sb,
                                                  const T *__restrict__ r, T *z,
                                                  const Seg *__restrict__ tab, int64_t row_base,
                                                  int64_t row_end, const int *__restrict__ done,
@@ -324,16 +395,17 @@ __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict_
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
     if (rl >= count) return;
     if (done && done[grid * R + v]) return;
-    pass_row<T, R, SKIP, NT, MODE>(n, val, col, r, z, row0 + rl, v, row_base, coarse, inj_coarse);
+    pass_row<T, R, SKIP, NT, MODE, D8>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse, inj_coarse);
 }
 
-template <typename T, int R, bool NT>
+template <typename T, int R, bool NT, bool D8>
 static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T *val, const int32_t *col,
-                    const T *r, T *z, const Seg *tab, int64_t rb, int64_t re, const int *done) {
+                    const int8_t *dcol, const Base27 &sb, const T *r, T *z, const Seg *tab, int64_t rb,
+                    int64_t re, const int *done) {
 #define MG_ZS_CASE(K, O)                                                                              \
     case K + 8 * O:                                                                                   \
-        k_pass<T, R, zs_mask(K, O), NT, 0><<<cnt, kBlock, 0, s>>>(n, val, col, r, z, tab, rb, re, done,  \
-                                                                  nullptr, nullptr);                \
+        k_pass<T, R, zs_mask(K, O), NT, 0, D8><<<cnt, kBlock, 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
+                                                                      done, nullptr, nullptr);      \
         break;
     switch (k + 8 * order) {
         MG_ZS_CASE(0, 0) MG_ZS_CASE(1, 0) MG_ZS_CASE(2, 0) MG_ZS_CASE(3, 0)
@@ -364,25 +436,30 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     }
     if (cnt == 0) return hipSuccess;
     const int32_t *ic = L.inj_coarse;
+    Base27 sb;
+    for (int t = 0; t < kW; ++t) sb.v[t] = L.dcol ? L.dbase_host[k * kW + t] : 0;
     if (mode == kPassZeroStart) {
         if (!L.zs_std || (R != 1 && R != 16)) return hipErrorInvalidValue;
         const int ord = P->colour_order;
+#define MG_ZS_LAUNCH(NT, D8)                                                                           \
+    if (R == 1) pass_zs<T, 1, NT, D8>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done); \
+    else pass_zs<T, 16, NT, D8>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done);
         if (L.stream_nt) {
-            if (R == 1) pass_zs<T, 1, true>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
-            else pass_zs<T, 16, true>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
+            if (L.dcol) { MG_ZS_LAUNCH(true, true) } else { MG_ZS_LAUNCH(true, false) }
         } else {
-            if (R == 1) pass_zs<T, 1, false>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
-            else pass_zs<T, 16, false>(k, ord, cnt, s, L.n, val, L.col, r, z, tab, rb, re, done);
+            if (L.dcol) { MG_ZS_LAUNCH(false, true) } else { MG_ZS_LAUNCH(false, false) }
         }
+#undef MG_ZS_LAUNCH
         return hipGetLastError();
     }
+#define MG_PASS_LAUNCH(NT, M, D8)                                                                      \
+    MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, D8><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, tab, \
+                                                                      rb, re, done, coarse, ic)));
 #define MG_PASS_MODE(M)                                                                                \
     if (L.stream_nt) {                                                                                 \
-        MG_DISPATCH_R(R, (k_pass<T, RR, 0u, true, M><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, r, z, tab, rb, \
-                                                                          re, done, coarse, ic)));   \
+        if (L.dcol) { MG_PASS_LAUNCH(true, M, true) } else { MG_PASS_LAUNCH(true, M, false) }            \
     } else {                                                                                           \
-        MG_DISPATCH_R(R, (k_pass<T, RR, 0u, false, M><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, r, z, tab, rb, \
-                                                                           re, done, coarse, ic)));  \
+        if (L.dcol) { MG_PASS_LAUNCH(false, M, true) } else { MG_PASS_LAUNCH(false, M, false) }          \
     }
     if (mode == kPassRestrict) {
         if (!L.fuse_transfers) return hipErrorInvalidValue;
@@ -393,6 +470,7 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     } else {
         MG_PASS_MODE(0)
     }
+#undef MG_PASS_LAUNCH
 #undef MG_PASS_MODE
     return hipGetLastError();
 }
@@ -419,8 +497,12 @@ template hipError_t launch_pass<float>(const mgpcg_problem *, int, int, int, con
 __device__ __forceinline__ bool grid_barrier(unsigned *flags, int B, unsigned epoch, int *err,
                                              long long spin_limit) {
     __shared__ int s_ok;
-    // the workgroup barrier waits until every wave's stores have reached its
-    // L2; one release fence then writes that L2 back for the other XCDs
+    // Every wave first waits until its own stores have completed at its L2
+    // (the memory counter is per wave, and the workgroup barrier alone does not
+    // wait for it); after the workgroup barrier one release fence then writes
+    // that L2 back for the other XCDs.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x < 64) {
         if (threadIdx.x == 0) {
@@ -453,121 +535,197 @@ __device__ __forceinline__ bool grid_barrier(unsigned *flags, int B, unsigned ep
     return s_ok != 0;
 }
 
-template <typename T, int R, uint32_t SKIP, int MODE>
+template <typename T, int R, bool D8, uint32_t SKIP, int MODE>
 __device__ __forceinline__ void coarse_phase(const CoarseLevel &lv, int k, T *coarse, int bid, int B) {
+    const int32_t *sb = D8 ? lv.dbase + k * kW : nullptr;
     const int64_t r0 = lv.coff[k], r1 = lv.coff[k + 1];
-    constexpr int rpb = kBlock / R;
+    const int rpb = blockDim.x / R;
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
     for (int64_t base = r0 + (int64_t)bid * rpb; base < r1; base += (int64_t)B * rpb) {
         const int64_t i = base + rl;
         if (i < r1)
-            pass_row<T, R, SKIP, false, MODE>(lv.n, (const T *)lv.val, lv.col, (const T *)lv.r, (T *)lv.z, i, v,
-                                             r0, coarse, lv.inj_coarse);
+            pass_row<T, R, SKIP, false, MODE, D8>(lv.n, (const T *)lv.val, lv.col, lv.dcol, sb, (const T *)lv.r,
+                                                 (T *)lv.z, i, v, r0, coarse, lv.inj_coarse);
     }
 }
 
-struct CoarseState {
-    unsigned epoch;
-    bool ok;
-    int bid, B;
-};
-
-__device__ __forceinline__ void coarse_sync(const CoarseArgs &A, CoarseState &st) {
-    ++st.epoch;
-    if (st.ok) st.ok = grid_barrier(A.flags, st.B, st.epoch, A.err, A.spin_limit);
-}
-
-// forward zero-start passes K..7 with their compile-time skip masks
-template <typename T, int R, int K>
-__device__ __forceinline__ void coarse_forward_zs(const CoarseArgs &A, const CoarseLevel &lv, CoarseState &st) {
-    if (st.ok) coarse_phase<T, R, zs_mask(K, 0), 0>(lv, K, nullptr, st.bid, st.B);
-    coarse_sync(A, st);
-    if constexpr (K < 7) coarse_forward_zs<T, R, K + 1>(A, lv, st);
+// separate restriction / refinement phases (when they cannot ride on a pass)
+template <typename T, int R, bool D8>
+__device__ __forceinline__ void coarse_restrict(const CoarseLevel &lv, T *rc, int bid, int B) {
+    const int rpb = blockDim.x / R;
+    const int rl = threadIdx.x / R, v = threadIdx.x % R;
+    for (int64_t base = (int64_t)bid * rpb; base < lv.n_inj; base += (int64_t)B * rpb) {
+        const int64_t t = base + rl;
+        if (t < lv.n_inj) {
+            const int64_t i = lv.inj_fine[t];
+            const int32_t *sb = D8 ? lv.dbase + colour_of(lv.coff, 8, i) * kW : nullptr;
+            T d;
+            const T acc = row_sum<T, R, 0u, false, D8>((const T *)lv.val, lv.col, lv.dcol, sb, lv.n, i,
+                                                      (const T *)lv.z, v, d);
+            rc[(int64_t)lv.inj_coarse[t] * R + v] = ((const T *)lv.r)[i * R + v] - acc;
+        }
+    }
 }
 
 template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void k_coarse_vcycle(CoarseArgs A) {
-    __shared__ unsigned s_base;
-    CoarseState st;
-    st.B = gridDim.x;
-    st.bid = xcd_remap(blockIdx.x, gridDim.x);
-    if (threadIdx.x == 0) s_base = __hip_atomic_load(A.epoch_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    st.epoch = s_base;
-    st.ok = true;
-    const int L = A.L, lc = A.lc;
-    bool first_sync = true;
-    auto sync = [&]() {
-        coarse_sync(A, st);
-        if (first_sync) {
-            first_sync = false;
-            // every workgroup has read the base by now
-            if (blockIdx.x == 0 && threadIdx.x == 0)
-                __hip_atomic_store(A.epoch_base, s_base + A.nbarriers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    };
-    // down: pre-smoothing, the last backward pass forms the coarse residual
-    for (int l = lc; l < L; ++l) {
-        const CoarseLevel &lv = A.lev[l];
-        if (st.ok) coarse_phase<T, R, zs_mask(0, 0), 0>(lv, 0, nullptr, st.bid, st.B);
-        sync();
-        coarse_forward_zs<T, R, 1>(A, lv, st);
-        for (int k = 7; k >= 1; --k) {
-            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, k, nullptr, st.bid, st.B);
-            sync();
-        }
-        if (l + 1 < L) {
-            if (st.ok) coarse_phase<T, R, 0u, 1>(lv, 0, (T *)A.lev[l + 1].r, st.bid, st.B);
-        } else {
-            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, 0, nullptr, st.bid, st.B);
-        }
-        if (l + 1 < L || lc < L - 1) sync();
-    }
-    // up: the first forward pass applies the refinement, then the sweep
-    for (int l = L - 2; l >= lc; --l) {
-        const CoarseLevel &lv = A.lev[l];
-        if (st.ok) coarse_phase<T, R, 0u, 2>(lv, 0, (T *)A.lev[l + 1].z, st.bid, st.B);
-        sync();
-        for (int k = 1; k < 8; ++k) {
-            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, k, nullptr, st.bid, st.B);
-            sync();
-        }
-        for (int k = 7; k >= 0; --k) {
-            if (st.ok) coarse_phase<T, R, 0u, 0>(lv, k, nullptr, st.bid, st.B);
-            if (!(l == lc && k == 0)) sync();
+__device__ __forceinline__ void coarse_prolong(const CoarseLevel &lv, const T *zc, int bid, int B) {
+    const int rpb = blockDim.x / R;
+    const int rl = threadIdx.x / R, v = threadIdx.x % R;
+    T *z = (T *)lv.z;
+    for (int64_t base = (int64_t)bid * rpb; base < lv.n_inj; base += (int64_t)B * rpb) {
+        const int64_t t = base + rl;
+        if (t < lv.n_inj) {
+            const int64_t o = (int64_t)lv.inj_fine[t] * R + v;
+            z[o] = z[o] + zc[(int64_t)lv.inj_coarse[t] * R + v];
         }
     }
 }
 
-hipError_t launch_coarse_vcycle(const mgpcg_problem *P, bool fp32, hipStream_t s) {
-    CoarseArgs A = P->coarse_args;
-    A.lc = P->coarse_lc;
-    A.L = P->L;
-    for (int l = A.lc; l < P->L; ++l) {
-        const Level &Lv = P->lev[l];
-        A.lev[l].val = fp32 ? (const void *)Lv.val32 : (const void *)Lv.val64;
+template <typename T, int R, bool D8, int ORD>
+__device__ __forceinline__ void coarse_run_phase(const CoarseArgs &A, int ph, int bid, int B) {
+    const int l = ph & 15, k = (ph >> 4) & 15, op = ph >> 8;
+    const CoarseLevel &lv = A.lev[l];
+    switch (op) {
+        case kOpPlain:
+            coarse_phase<T, R, D8, 0u, 0>(lv, k, nullptr, bid, B);
+            break;
+        case kOpZeroStart:
+            switch (k) {
+#define MG_ZS_PHASE(K) \
+    case K: coarse_phase<T, R, D8, zs_mask(K, ORD), 0>(lv, K, nullptr, bid, B); break;
+                MG_ZS_PHASE(0) MG_ZS_PHASE(1) MG_ZS_PHASE(2) MG_ZS_PHASE(3)
+                MG_ZS_PHASE(4) MG_ZS_PHASE(5) MG_ZS_PHASE(6) MG_ZS_PHASE(7)
+#undef MG_ZS_PHASE
+                default: break;
+            }
+            break;
+        case kOpFusedRestrict:
+            coarse_phase<T, R, D8, 0u, 1>(lv, k, (T *)A.lev[l + 1].r, bid, B);
+            break;
+        case kOpFusedProlong:
+            coarse_phase<T, R, D8, 0u, 2>(lv, k, (T *)A.lev[l + 1].z, bid, B);
+            break;
+        case kOpRestrict:
+            coarse_restrict<T, R, D8>(lv, (T *)A.lev[l + 1].r, bid, B);
+            break;
+        case kOpProlong:
+            coarse_prolong<T, R>(lv, (const T *)A.lev[l + 1].z, bid, B);
+            break;
+        default:
+            break;
     }
-    const int B = P->coarse_blocks;
-    if (P->R == 1) {
-        if (fp32) k_coarse_vcycle<float, 1><<<B, kBlock, 0, s>>>(A);
-        else k_coarse_vcycle<double, 1><<<B, kBlock, 0, s>>>(A);
-    } else if (P->R == 16) {
-        if (fp32) k_coarse_vcycle<float, 16><<<B, kBlock, 0, s>>>(A);
-        else k_coarse_vcycle<double, 16><<<B, kBlock, 0, s>>>(A);
+}
+
+// Executes the host-built phase program (level, colour, operation) with one
+// grid barrier between consecutive phases.
+template <typename T, int R, bool D8, int ORD>
+__global__ __launch_bounds__(kBlock) void k_coarse_vcycle(CoarseArgs A) {
+    __shared__ unsigned s_base;
+    const int B = gridDim.x;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    if (threadIdx.x == 0) s_base = __hip_atomic_load(A.epoch_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    unsigned epoch = s_base;
+    bool ok = true;
+    for (int p = 0; p < A.nphases; ++p) {
+        if (ok) coarse_run_phase<T, R, D8, ORD>(A, A.phase[p], bid, B);
+        if (p + 1 == A.nphases) break;
+        ++epoch;
+        if (ok) ok = grid_barrier(A.flags, B, epoch, A.err, A.spin_limit);
+        // after the first barrier every workgroup has read the base: advance
+        // it past this launch's epochs for the next launch
+        if (p == 0 && blockIdx.x == 0 && threadIdx.x == 0)
+            __hip_atomic_store(A.epoch_base, s_base + (unsigned)(A.nphases - 1), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Coarsest level, one workgroup: its symmetric sweep (zero-start forward
+// pass, backward pass) with r and z held in LDS.  The 16 colour passes are
+// separated by workgroup barriers instead of kernel launches, and the 27
+// gathers of every row read LDS; only the operator rows come from memory.
+constexpr int kTailBlock = 512;
+template <typename T, bool D8, int ORD>
+__global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *__restrict__ val,
+                                                            const int32_t *__restrict__ col,
+                                                            const int8_t *__restrict__ dcol,
+                                                            const int32_t *__restrict__ dbase, CoffTable ct,
+                                                            const T *__restrict__ r, T *__restrict__ z) {
+    extern __shared__ char tail_lds[];
+    T *rs = (T *)tail_lds;
+    T *zs = rs + n;
+    for (int64_t i = threadIdx.x; i < n; i += kTailBlock) rs[i] = r[i];
+    __syncthreads();
+    // forward, zero start: colour k reads only colours < k
+#define MG_TAIL_FWD(K)                                                                                 \
+    for (int64_t i = ct.coff[K] + threadIdx.x; i < ct.coff[K + 1]; i += kTailBlock)                     \
+        pass_row<T, 1, zs_mask(K, ORD), false, 0, D8>(n, val, col, dcol, D8 ? dbase + K * kW : nullptr, rs, zs, \
+                                                      i, 0, 0, nullptr, nullptr);                      \
+    __syncthreads();
+    MG_TAIL_FWD(0) MG_TAIL_FWD(1) MG_TAIL_FWD(2) MG_TAIL_FWD(3)
+    MG_TAIL_FWD(4) MG_TAIL_FWD(5) MG_TAIL_FWD(6) MG_TAIL_FWD(7)
+#undef MG_TAIL_FWD
+    for (int k = 7; k >= 0; --k) {
+        for (int64_t i = ct.coff[k] + threadIdx.x; i < ct.coff[k + 1]; i += kTailBlock)
+            pass_row<T, 1, 0u, false, 0, D8>(n, val, col, dcol, D8 ? dbase + k * kW : nullptr, rs, zs, i, 0, 0,
+                                             nullptr, nullptr);
+        __syncthreads();
+    }
+    for (int64_t i = threadIdx.x; i < n; i += kTailBlock) z[i] = zs[i];
+}
+
+hipError_t launch_coarse_tail(const mgpcg_problem *P, bool fp32, hipStream_t s) {
+    const int l = P->L - 1;
+    const Level &L = P->lev[l];
+    if (P->R != 1 || L.ncol != 8) return hipErrorInvalidValue;
+    const CoffTable ct = coff_table(L);
+    const size_t lds = (size_t)L.n * 2 * (fp32 ? sizeof(float) : sizeof(double));
+#define MG_TAIL(T, VAL, D8)                                                                            \
+    if (P->colour_order)                                                                               \
+        k_coarse_tail<T, D8, 1><<<1, kTailBlock, lds, s>>>(L.n, VAL, L.col, L.dcol, L.dbase, ct, (const T *)L.r, \
+                                                          (T *)L.z);                                    \
+    else                                                                                               \
+        k_coarse_tail<T, D8, 0><<<1, kTailBlock, lds, s>>>(L.n, VAL, L.col, L.dcol, L.dbase, ct, (const T *)L.r, \
+                                                          (T *)L.z);
+    if (fp32) {
+        if (L.dcol) { MG_TAIL(float, L.val32, true) } else { MG_TAIL(float, L.val32, false) }
     } else {
-        return hipErrorInvalidValue;
+        if (L.dcol) { MG_TAIL(double, L.val64, true) } else { MG_TAIL(double, L.val64, false) }
     }
+#undef MG_TAIL
     return hipGetLastError();
 }
 
-int coarse_vcycle_occupancy(int R, bool fp32) {
+hipError_t launch_coarse_vcycle(const mgpcg_problem *P, bool fp32, hipStream_t s) {
+    const CoarseArgs &A = P->coarse_args;
+    const int B = P->coarse_blocks;
+    if (P->R != 1 || A.nphases < 1) return hipErrorInvalidValue;
+#define MG_COARSE(T, D8)                                                                               \
+    if (P->colour_order) k_coarse_vcycle<T, 1, D8, 1><<<B, kBlock, 0, s>>>(A);                           \
+    else k_coarse_vcycle<T, 1, D8, 0><<<B, kBlock, 0, s>>>(A);
+    if (fp32) {
+        if (A.d8) { MG_COARSE(float, true) } else { MG_COARSE(float, false) }
+    } else {
+        if (A.d8) { MG_COARSE(double, true) } else { MG_COARSE(double, false) }
+    }
+#undef MG_COARSE
+    return hipGetLastError();
+}
+
+int coarse_vcycle_occupancy(int R, bool fp32, bool d8, int order) {
+    if (R != 1) return 0;
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
-    if (R == 1) e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<float, 1>, kBlock, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<double, 1>, kBlock, 0);
-    else if (R == 16)
-        e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<float, 16>, kBlock, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<double, 16>, kBlock, 0);
+#define MG_OCC(T, D8, O) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<T, 1, D8, O>, kBlock, 0);
+#define MG_OCC2(T, D8)                                                                                  \
+    if (order) { MG_OCC(T, D8, 1) } else { MG_OCC(T, D8, 0) }
+    if (fp32) {
+        if (d8) { MG_OCC2(float, true) } else { MG_OCC2(float, false) }
+    } else {
+        if (d8) { MG_OCC2(double, true) } else { MG_OCC2(double, false) }
+    }
+#undef MG_OCC2
+#undef MG_OCC
     return e == hipSuccess ? nb : 0;
 }
 
@@ -576,9 +734,11 @@ int coarse_vcycle_occupancy(int R, bool fp32) {
 // rc = inject(r - A z): only the injection rows of the residual are formed.
 // Threads walk the injection rows in fine order (coalesced operator reads)
 // and scatter into the coarse vector.
-template <typename T, int R, bool NT>
+template <typename T, int R, bool NT, bool D8>
 __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restrict__ val,
                                                      const int32_t *__restrict__ col,
+                                                     const int8_t *__restrict__ dcol,
+                                                     const int32_t *__restrict__ dbase, CoffTable ct,
                                                      const T *__restrict__ r, const T *__restrict__ z,
                                                      T *__restrict__ rc,
                                                      const int32_t *__restrict__ inj_fine,
@@ -590,7 +750,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restr
     int v = (int)(gid % R);
     int64_t i = inj_fine[t];
     T d;
-    const T acc = row_sum<T, R, 0u, NT>(val, col, n, i, z, v, d);
+    const int32_t *sb = D8 ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
+    const T acc = row_sum<T, R, 0u, NT, D8>(val, col, dcol, sb, n, i, z, v, d);
     rc[(int64_t)inj_coarse[t] * R + v] = r[i * R + v] - acc;
 }
 
@@ -600,13 +761,16 @@ hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, cons
     const Level &L = P->lev[level];
     int64_t work = L.n_inj * P->R;
     if (work == 0) return hipSuccess;
+    const CoffTable ct = coff_table(L);
+#define MG_RESTRICT(NT, D8)                                                                             \
+    MG_DISPATCH_R(P->R, (k_restrict<T, RR, NT, D8><<<nblocks(work), kBlock, 0, s>>>(                    \
+                            L.n, val, L.col, L.dcol, L.dbase, ct, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
     if (L.stream_nt) {
-        MG_DISPATCH_R(P->R, (k_restrict<T, RR, true><<<nblocks(work), kBlock, 0, s>>>(
-                                L.n, val, L.col, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
+        if (L.dcol) { MG_RESTRICT(true, true) } else { MG_RESTRICT(true, false) }
     } else {
-        MG_DISPATCH_R(P->R, (k_restrict<T, RR, false><<<nblocks(work), kBlock, 0, s>>>(
-                                L.n, val, L.col, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
+        if (L.dcol) { MG_RESTRICT(false, true) } else { MG_RESTRICT(false, false) }
     }
+#undef MG_RESTRICT
     return hipGetLastError();
 }
 template hipError_t launch_restrict<double>(const mgpcg_problem *, int, const double *, const double *,
@@ -748,9 +912,11 @@ __device__ __forceinline__ bool grid_done(const int *done, int g) {
 }
 
 // r = b - A x, partial ||r||^2
-template <int R>
+template <int R, bool D8>
 __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const double *__restrict__ val,
                                                           const int32_t *__restrict__ col,
+                                                          const int8_t *__restrict__ dcol,
+                                                          const int32_t *__restrict__ dbase,
                                                           const double *__restrict__ b,
                                                           const double *__restrict__ x,
                                                           double *__restrict__ r, const Seg *__restrict__ tab,
@@ -762,7 +928,8 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
     if (rl < e.count) {
         const int64_t i = e.row0 + rl;
         double d;
-        const double s = row_sum<double, R, 0u, true>(val, col, n, i, x, v, d);
+        const int32_t *sb = D8 ? dbase + e.colour * kW : nullptr;
+        const double s = row_sum<double, R, 0u, true, D8>(val, col, dcol, sb, n, i, x, v, d);
         const double ri = b[i * R + v] - s;
         r[i * R + v] = ri;
         acc = ri * ri;
@@ -811,9 +978,11 @@ __global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ 
 }
 
 // q = A p, partial <p, q>
-template <int R>
+template <int R, bool D8>
 __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__restrict__ val,
                                                     const int32_t *__restrict__ col,
+                                                    const int8_t *__restrict__ dcol,
+                                                    const int32_t *__restrict__ dbase,
                                                     const double *__restrict__ p, double *__restrict__ q,
                                                     const Seg *__restrict__ tab, double *__restrict__ partials,
                                                     const int *__restrict__ done) {
@@ -825,7 +994,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
     if (rl < e.count) {
         const int64_t i = e.row0 + rl;
         double d;
-        const double s = row_sum<double, R, 0u, true>(val, col, n, i, p, v, d);
+        const int32_t *sb = D8 ? dbase + e.colour * kW : nullptr;
+        const double s = row_sum<double, R, 0u, true, D8>(val, col, dcol, sb, n, i, p, v, d);
         q[i * R + v] = s;
         acc = p[i * R + v] * s;
     }
@@ -940,8 +1110,15 @@ static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hi
 // rows per thread (table 1).
 hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
-    MG_DISPATCH_R(P->R, (k_init_residual<RR><<<P->n_red[0], kBlock, 0, s>>>(
-                            L.n, L.val64, L.col, P->b, P->x, P->r, P->red_tab[0], P->sc.partials)));
+    if (L.dcol) {
+        MG_DISPATCH_R(P->R, (k_init_residual<RR, true><<<P->n_red[0], kBlock, 0, s>>>(
+                                L.n, L.val64, L.col, L.dcol, L.dbase, P->b, P->x, P->r, P->red_tab[0],
+                                P->sc.partials)));
+    } else {
+        MG_DISPATCH_R(P->R, (k_init_residual<RR, false><<<P->n_red[0], kBlock, 0, s>>>(
+                                L.n, L.val64, L.col, L.dcol, L.dbase, P->b, P->x, P->r, P->red_tab[0],
+                                P->sc.partials)));
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kInit>(P, 0, 0.0, 0, s);
@@ -959,9 +1136,15 @@ hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s) {
 }
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
-    MG_DISPATCH_R(P->R, (k_spmv_pq<RR><<<P->n_red[0], kBlock, 0, s>>>(L.n, L.val64, L.col, P->p, P->q,
-                                                                      P->red_tab[0], P->sc.partials,
-                                                                      P->sc.done)));
+    if (L.dcol) {
+        MG_DISPATCH_R(P->R, (k_spmv_pq<RR, true><<<P->n_red[0], kBlock, 0, s>>>(
+                                L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials,
+                                P->sc.done)));
+    } else {
+        MG_DISPATCH_R(P->R, (k_spmv_pq<RR, false><<<P->n_red[0], kBlock, 0, s>>>(
+                                L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials,
+                                P->sc.done)));
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kPq>(P, 0, 0.0, 0, s);

@@ -181,6 +181,32 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(upload(&P->d_natoff[l], natoff, s));
         if (l == 0) ST_TRY(upload(&P->d_natoff0, natoff, s));
 
+        // per-colour column bases for delta-coded columns (single grid):
+        // base[k][s] = column - row of the first row of colour k that has a
+        // neighbour in slot s
+        if (G == 1 && P->delta_cols) {
+            const LevelGrid &lg = Lv.grids[0];
+            std::vector<int32_t> base(8 * kW, 0);
+            for (int k = 0; k < Lv.ncol; ++k) {
+                int missing = kW;
+                std::vector<char> have(kW, 0);
+                for (int64_t i = Lv.coff[k]; i < Lv.coff[k + 1] && missing > 0; ++i) {
+                    const int64_t q = iperm[i];
+                    const int ix = (int)(q % lg.nx), iy = (int)((q / lg.nx) % lg.ny), iz = (int)(q / ((int64_t)lg.nx * lg.ny));
+                    for (int sl = 0; sl < kW; ++sl) {
+                        if (have[sl]) continue;
+                        const int jx = ix + sl % 3 - 1, jy = iy + (sl / 3) % 3 - 1, jz = iz + sl / 9 - 1;
+                        if (jx < 0 || jx >= lg.nx || jy < 0 || jy >= lg.ny || jz < 0 || jz >= lg.nz) continue;
+                        base[k * kW + sl] = (int32_t)(perm[jx + (int64_t)lg.nx * (jy + (int64_t)lg.ny * jz)] - i);
+                        have[sl] = 1;
+                        --missing;
+                    }
+                }
+            }
+            ST_TRY(upload(&Lv.dbase, base, s));
+            Lv.dbase_host = base;
+        }
+
         // colour-pass tables: one workgroup per kBlock/R rows, grid-homogeneous
         std::vector<Seg> tab;
         Lv.pass_first.assign(Lv.ncol + 1, 0);
@@ -193,7 +219,8 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
                     Seg e;
                     e.row0 = lg.seg_off[k] + a;
                     e.count = (int32_t)std::min<int64_t>(rows_per_block, lg.seg_len[k] - a);
-                    e.grid = g;
+                    e.grid = (int16_t)g;
+                    e.colour = (int16_t)k;
                     tab.push_back(e);
                 }
             }
@@ -306,6 +333,28 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             Lv.z = z64;
         }
         HIP_TRY(launch_build_ell(P, l, theta, s));
+        if (Lv.dbase) {
+            // try the compact column format; keep int32 columns if any delta is out of range
+            ST_TRY(dalloc(&Lv.dcol, Lv.n * kW));
+            int64_t *coff_dev = nullptr;
+            int *bad = nullptr;
+            std::vector<int64_t> coffv(Lv.coff.begin(), Lv.coff.end());
+            ST_TRY(upload(&coff_dev, coffv, s));
+            ST_TRY(dalloc(&bad, 1));
+            HIP_TRY(launch_fill_i(bad, 1, 0, s));
+            HIP_TRY(launch_delta_encode(P, l, coff_dev, bad, s));
+            int hbad = 1;
+            HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            dfree(coff_dev);
+            dfree(bad);
+            if (hbad) {
+                dfree(Lv.dcol);
+                dfree(Lv.dbase);
+            } else {
+                dfree(Lv.col);
+            }
+        }
     }
 
     // level-0 reduction tables: grid by grid, chunks of kBlock/R rows (one
@@ -325,7 +374,8 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
                         Seg e;
                         e.row0 = lg.seg_off[k] + a;
                         e.count = (int32_t)std::min<int64_t>(rows, lg.seg_len[k] - a);
-                        e.grid = g;
+                        e.grid = (int16_t)g;
+                        e.colour = (int16_t)k;
                         tab.push_back(e);
                     }
             }
@@ -356,45 +406,82 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(dalloc(&sc.ndone, 1));
         ST_TRY(dalloc(&sc.partials, max_blocks * R));
     }
-    // persistent coarse-level V-cycle: canonical colour order, standard
-    // 8-colour masks on every coarse level, refinement/restriction fused on
-    // the coarse levels that have a coarser one
+    // persistent coarse-level V-cycle (levels 1..L-1 in one launch) and the
+    // single-workgroup tail (the smallest levels): one right-hand side,
+    // standard 8-colour zero-start masks, one column format
     {
-        bool ok = L >= 2 && P->colour_order == 0 && (R == 1 || R == 16);
-        for (int l = 1; l < L && ok; ++l) ok = P->lev[l].zs_std && P->lev[l].ncol == 8;
-        for (int l = 1; l + 1 < L && ok; ++l) ok = P->lev[l].fuse_transfers;
         const bool fp32 = P->mg_dtype == MGPCG_FP32;
+        auto eligible = [&](int from) {
+            bool ok = from >= 1 && from < L && R == 1;
+            for (int l = from; l < L && ok; ++l) ok = P->lev[l].zs_std && P->lev[l].ncol == 8;
+            const bool d8 = ok && P->lev[from].dcol != nullptr;
+            for (int l = from; l < L && ok; ++l) ok = (P->lev[l].dcol != nullptr) == d8;
+            return ok;
+        };
+        // the phase program of the V-cycle of Listing 1 from level `from` down
+        auto program = [&](int from, CoarseArgs &A) -> bool {
+            std::vector<uint16_t> prog;
+            auto ph = [&](int l, int k, int op) { prog.push_back((uint16_t)(l | (k << 4) | (op << 8))); };
+            for (int l = from; l < L; ++l) {
+                const bool coarser = l + 1 < L;
+                const bool fuse = coarser && P->lev[l].fuse_transfers;
+                for (int k = 0; k < 8; ++k) ph(l, k, kOpZeroStart);
+                for (int k = 7; k >= 1; --k) ph(l, k, kOpPlain);
+                ph(l, 0, fuse ? kOpFusedRestrict : kOpPlain);
+                if (coarser && !fuse) ph(l, 0, kOpRestrict);
+            }
+            for (int l = L - 2; l >= from; --l) {
+                const bool fuse = P->lev[l].fuse_transfers;
+                if (!fuse) ph(l, 0, kOpProlong);
+                ph(l, 0, fuse ? kOpFusedProlong : kOpPlain);
+                for (int k = 1; k < 8; ++k) ph(l, k, kOpPlain);
+                for (int k = 7; k >= 0; --k) ph(l, k, kOpPlain);
+            }
+            if ((int)prog.size() > kMaxPhases) return false;
+            memset(&A, 0, sizeof(A));
+            A.d8 = P->lev[from].dcol != nullptr;
+            for (int l = from; l < L; ++l) {
+                const Level &Lv = P->lev[l];
+                CoarseLevel &cl = A.lev[l];
+                cl.n = Lv.n;
+                cl.val = fp32 ? (const void *)Lv.val32 : (const void *)Lv.val64;
+                cl.col = Lv.col;
+                cl.dcol = Lv.dcol;
+                cl.dbase = Lv.dbase;
+                cl.r = Lv.r;
+                cl.z = Lv.z;
+                cl.inj_fine = Lv.inj_fine;
+                cl.inj_coarse = Lv.inj_coarse;
+                cl.n_inj = Lv.n_inj;
+                for (int k = 0; k <= 8; ++k) cl.coff[k] = Lv.coff[std::min(k, Lv.ncol)];
+            }
+            A.nphases = (int)prog.size();
+            for (size_t t = 0; t < prog.size(); ++t) A.phase[t] = prog[t];
+            return true;
+        };
+        auto max_colour_rows = [&](int l) {
+            int64_t m = 0;
+            for (int k = 0; k < P->lev[l].ncol; ++k) m = std::max<int64_t>(m, P->lev[l].coff[k + 1] - P->lev[l].coff[k]);
+            return m;
+        };
+
+        const int lc = 1;
+        bool ok = eligible(lc);
         int ncu = 0;
         if (ok && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess) ok = false;
-        const int occ = ok ? coarse_vcycle_occupancy(R, fp32) : 0;
+        const int occ = ok ? coarse_vcycle_occupancy(R, fp32, P->lev[lc].dcol != nullptr, P->colour_order) : 0;
         if (ok && occ < 1) ok = false;
+        if (ok) ok = program(lc, P->coarse_args);
         if (ok) {
-            const int lc = 1;
-            int64_t maxrows = 0;
-            const Level &Lc = P->lev[lc];
-            for (int k = 0; k < Lc.ncol; ++k) maxrows = std::max<int64_t>(maxrows, Lc.coff[k + 1] - Lc.coff[k]);
-            const int64_t want = (maxrows + kBlock / R - 1) / (kBlock / R);
+            const int64_t want = (max_colour_rows(lc) + kBlock / R - 1) / (kBlock / R);
             int B = (int)std::max<int64_t>(1, std::min<int64_t>(want, ncu));
             if (const char *env = getenv("MGPCG_COARSE_BLOCKS")) {  // tuning override
-                const int b = atoi(env);
-                if (b >= 1 && b <= ncu) B = b;
+                const int bb = atoi(env);
+                if (bb >= 1 && bb <= ncu) B = bb;
             }
             P->coarse_lc = lc;
             P->coarse_blocks = B;
             CoarseArgs &A = P->coarse_args;
-            memset(&A, 0, sizeof(A));
-            for (int l = lc; l < L; ++l) {
-                const Level &Lv = P->lev[l];
-                CoarseLevel &cl = A.lev[l];
-                cl.n = Lv.n;
-                cl.col = Lv.col;
-                cl.r = Lv.r;
-                cl.z = Lv.z;
-                cl.inj_coarse = Lv.inj_coarse;
-                for (int k = 0; k <= 8; ++k) cl.coff[k] = Lv.coff[std::min(k, Lv.ncol)];
-            }
-            const int phases = 16 * (L - lc) + 16 * (L - 1 - lc);
-            A.nbarriers = (unsigned)(phases - 1);
             ST_TRY(dalloc(&P->coarse_flags, (int64_t)B + 1));
             ST_TRY(dalloc(&P->coarse_err, 1));
             A.flags = P->coarse_flags;
@@ -405,6 +492,16 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             HIP_TRY(launch_fill_i(P->coarse_err, 1, 0, s));
         }
         P->coarse_ok = ok;
+
+        // tail: the coarsest level, when its r and z fit in one workgroup's
+        // LDS and it has the standard 8-colour numbering
+        int64_t tail_bytes = 64 << 10;
+        if (const char *env = getenv("MGPCG_TAIL_BYTES")) tail_bytes = atoll(env);  // tuning override
+        const Level &Lt = P->lev[L - 1];
+        const int64_t need = Lt.n * 2 * (fp32 ? 4 : 8);
+        P->tail_ok = L >= 2 && R == 1 && Lt.zs_std && Lt.ncol == 8 && need <= tail_bytes &&
+                     need <= (64 << 10);
+        P->tail_lw = P->tail_ok ? L - 1 : L;
     }
     HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int), hipHostMallocDefault));
     HIP_TRY(hipStreamSynchronize(s));
@@ -419,7 +516,8 @@ void free_problem(mgpcg_problem *P) {
     (void)hipSetDevice(P->device);
     (void)hipDeviceSynchronize();
     for (auto &Lv : P->lev) {
-        dfree(Lv.val64); dfree(Lv.val32); dfree(Lv.col); dfree(Lv.perm); dfree(Lv.iperm);
+        dfree(Lv.val64); dfree(Lv.val32); dfree(Lv.col); dfree(Lv.dcol); dfree(Lv.dbase); dfree(Lv.perm);
+        dfree(Lv.iperm);
         dfree(Lv.grid_of_nat); dfree(Lv.pass_tab); dfree(Lv.inj_fine); dfree(Lv.inj_coarse);
         dfree(Lv.r); dfree(Lv.z); dfree(Lv.t0); dfree(Lv.t1); dfree(Lv.t2);
     }
@@ -474,7 +572,9 @@ const float *level_val<float>(const mgpcg_problem *P, int l) { return P->lev[l].
 template <typename T>
 hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, hipStream_t s) {
     const bool persistent = P->coarse_ok && P->coarse_mode == 1;
-    const int L = persistent ? P->coarse_lc : P->L;
+    const bool tail = !persistent && P->tail_ok;
+    // levels below L run one kernel per pass; the rest in one launch
+    const int L = persistent ? P->coarse_lc : (tail ? P->tail_lw : P->L);
     auto rl = [&](int l) -> T * { return l == 0 ? const_cast<T *>(r0) : (T *)P->lev[l].r; };
     auto zl = [&](int l) -> T * { return l == 0 ? z0 : (T *)P->lev[l].z; };
     hipError_t e;
@@ -497,7 +597,8 @@ hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, h
             return e;
     }
     if (persistent && (e = launch_coarse_vcycle(P, sizeof(T) == 4, s)) != hipSuccess) return e;
-    for (int l = (persistent ? L - 1 : L - 2); l >= 0; --l) {
+    if (tail && (e = launch_coarse_tail(P, sizeof(T) == 4, s)) != hipSuccess) return e;
+    for (int l = (persistent || tail ? L - 1 : L - 2); l >= 0; --l) {
         const bool fuse = P->lev[l].fuse_transfers;
         if (!fuse && (e = launch_prolong<T>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
         if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), fuse ? kPassProlong : kPassPlain, kPassPlain,
@@ -660,7 +761,7 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     if (!out) return fail(MGPCG_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!cfg || !cfg->dims) return fail(MGPCG_ERR_INVALID_ARG, "config or dims is NULL");
-    if (cfg->ngrids < 1) return fail(MGPCG_ERR_DIMS, "ngrids must be >= 1");
+    if (cfg->ngrids < 1 || cfg->ngrids > 32767) return fail(MGPCG_ERR_DIMS, "ngrids must be in 1..32767");
     if (cfg->levels < 1 || cfg->levels > MGPCG_MAX_LEVELS)
         return fail(MGPCG_ERR_DIMS, "levels must be in 1.." + std::to_string(MGPCG_MAX_LEVELS));
     const int R = cfg->nrhs;
@@ -701,6 +802,7 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     P->mg_dtype = cfg->mg_dtype;
     P->colour_order = cfg->colour_order;
     P->dims0.assign(cfg->dims, cfg->dims + 3 * cfg->ngrids);
+    if (const char *env = getenv("MGPCG_DELTA_COLS")) P->delta_cols = atoi(env) != 0;  // tuning override
     mgpcg_status st = build_hierarchy(P, cfg->theta, stream);
     if (st != MGPCG_OK) {
         std::string msg = g_err;

@@ -33,7 +33,8 @@ constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
 struct Seg {
     int64_t row0;
     int32_t count;
-    int32_t grid;
+    int16_t grid;
+    int16_t colour;
 };
 
 struct LevelGrid {  // one grid at one level
@@ -54,7 +55,12 @@ struct Level {
 
     double *val64 = nullptr;  // [27][n], FP64 operator (level 0 always; all levels if FP64 V-cycle)
     float *val32 = nullptr;   // [27][n], FP32 operator (FP32 V-cycle)
-    int32_t *col = nullptr;   // [27][n]
+    int32_t *col = nullptr;   // [27][n] absolute columns (NULL when delta-coded)
+    // delta-coded columns: col(i,s) = i + dbase[colour(i)*27 + s] + dcol[s*n+i];
+    // used when every real entry's delta fits in int8 (single-grid problems)
+    int8_t *dcol = nullptr;   // [27][n]
+    int32_t *dbase = nullptr; // [8][27]
+    std::vector<int32_t> dbase_host;
     int32_t *perm = nullptr;  // natural packed row -> internal row
     int32_t *iperm = nullptr; // internal row -> natural packed row
     int32_t *grid_of_nat = nullptr;  // natural packed row -> grid (only when G > 1)
@@ -86,14 +92,24 @@ struct CoarseLevel {
     int64_t n;
     const void *val;
     const int32_t *col;
+    const int8_t *dcol;
+    const int32_t *dbase;
     void *r, *z;
-    const int32_t *inj_coarse;  // to level+1, indexed by row - coff[0]
+    const int32_t *inj_fine;    // injection rows (to level+1), sorted
+    const int32_t *inj_coarse;  // their coarse rows
+    int64_t n_inj;
     int64_t coff[9];
 };
+// operations of the persistent coarse-level kernel's phase program; a phase
+// is level | colour << 4 | op << 8
+enum CoarseOp { kOpPlain = 0, kOpZeroStart = 1, kOpFusedRestrict = 2, kOpFusedProlong = 3,
+                kOpRestrict = 4, kOpProlong = 5 };
+constexpr int kMaxPhases = 320;
 struct CoarseArgs {
     CoarseLevel lev[MGPCG_MAX_LEVELS];
-    int lc, L;
-    unsigned nbarriers;
+    int nphases;
+    uint16_t phase[kMaxPhases];
+    bool d8;              // every coarse level is delta-coded
     unsigned *flags;       // one per workgroup
     unsigned *epoch_base;  // advanced by the kernel at each launch
     int *err;              // set when a barrier wait times out
@@ -114,6 +130,7 @@ struct mgpcg_problem {
     int G = 1, R = 1, S = 1, L = 1;
     int mg_dtype = MGPCG_FP64;
     int colour_order = 0;
+    bool delta_cols = true;  // allow int8 delta-coded columns (single-grid problems)
     std::vector<int> dims0;  // 3*G, level 0
     std::vector<mg::Level> lev;
 
@@ -146,6 +163,9 @@ struct mgpcg_problem {
     int coarse_blocks = 0;
     mg::CoarseArgs coarse_args{};
     unsigned *coarse_flags = nullptr;   // coarse_blocks + 1 (last: epoch base)
+    // coarsest level in one workgroup with r and z in LDS
+    bool tail_ok = false;
+    int tail_lw = 0;
     int *coarse_err = nullptr;
 
     // captured iteration graph

@@ -330,9 +330,13 @@ def test_128cubed_pcg_history_golden(mg, p128):
 
 @pytest.mark.parametrize("dims", [(16, 16, 16), (24, 16, 32)])
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
-def test_coarse_persistent_equals_per_pass(mg, dims, dtype):
-    o = Oracle(*dims)
-    p = mg.Problem(dims, mg_dtype=dtype)
+@pytest.mark.parametrize("order", [0, 1])
+def test_coarse_persistent_equals_per_pass(mg, dims, dtype, order):
+    # Under colour order 0 the restricted residual is ~0 (the coarse levels only
+    # add rounding), so order 1 is the case in which a coarse-level mistake
+    # would show; both are compared bit for bit with the oracle.
+    o = Oracle(*dims, colour_order=order)
+    p = mg.Problem(dims, mg_dtype=dtype, colour_order=order)
     r = dev(inputs.uniform(60, o.n()))
     outs = []
     for mode in (0, 1, 0, 1):
@@ -344,20 +348,22 @@ def test_coarse_persistent_equals_per_pass(mg, dims, dtype):
         np.testing.assert_array_equal(z, outs[0])
     ref = o.vcycle(host(r)) if dtype == "fp64" else o.vcycle32(host(r))
     np.testing.assert_array_equal(outs[1], ref)
+    np.testing.assert_array_equal(outs[0], ref)
     b = p.make_rhs_ones()
     hs = []
     for mode in (1, 0):
         p.set_coarse_mode(mode)
         x, h, its, st = p.solve(b, max_iters=30)
-        assert st == mg.OK
+        assert st == mg.OK and p.check() == mg.OK
         hs.append((host(x), h.copy()))
     np.testing.assert_array_equal(hs[0][0], hs[1][0])
     np.testing.assert_array_equal(hs[0][1], hs[1][1])
 
 
-def test_coarse_persistent_batched_and_multi_rhs(mg):
+@pytest.mark.parametrize("order", [0, 1])
+def test_coarse_persistent_batched_and_multi_rhs(mg, order):
     dims = [(16, 16, 16), (24, 16, 32), (8, 16, 8)]
-    p = mg.Problem(dims)
+    p = mg.Problem(dims, colour_order=order)
     sizes = [a * b * c for a, b, c in dims]
     r = dev(inputs.batch_rhs(61, sizes))
     p.set_coarse_mode(0)
@@ -366,7 +372,14 @@ def test_coarse_persistent_batched_and_multi_rhs(mg):
     z1 = host(p.vcycle(r))
     assert p.check() == mg.OK
     np.testing.assert_array_equal(z0, z1)
-    pm = mg.Problem((16, 16, 16), nrhs=16)
+    oras = [Oracle(*d, colour_order=order) for d in dims]
+    rr = host(r)
+    off = 0
+    for o in oras:
+        np.testing.assert_array_equal(z1[off:off + o.n()], o.vcycle(rr[off:off + o.n()]))
+        off += o.n()
+    # 16 right-hand sides: the persistent mode is not used (falls back)
+    pm = mg.Problem((16, 16, 16), nrhs=16, colour_order=order)
     B = dev(inputs.multi_rhs(62, 16, 4096))
     pm.set_coarse_mode(0)
     z0 = host(pm.vcycle(B))
@@ -374,3 +387,45 @@ def test_coarse_persistent_batched_and_multi_rhs(mg):
     z1 = host(pm.vcycle(B))
     assert pm.check() == mg.OK
     np.testing.assert_array_equal(z0, z1)
+
+
+# ------------------------------------------------- column formats (int32 / int8 deltas)
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (24, 16, 32)])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_delta_coded_columns_identical(mg, dims, dtype, monkeypatch):
+    r = dev(inputs.uniform(70, int(np.prod(dims))))
+    outs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("MGPCG_DELTA_COLS", flag)
+        p = mg.Problem(dims, mg_dtype=dtype)
+        z = host(p.vcycle(r))
+        y = host(p.spmv(r))
+        x, h, its, st = p.solve(r, max_iters=20)
+        outs.append((z, y, host(x), h.copy()))
+        p.close()
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+# ------------------------------- single-workgroup tail of the smallest levels
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (32, 32, 32)])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("order", [0, 1])
+def test_tail_equals_per_pass(mg, dims, dtype, order, monkeypatch):
+    o = Oracle(*dims, colour_order=order)
+    r = inputs.uniform(71, o.n())
+    ref = o.vcycle(r) if dtype == "fp64" else o.vcycle32(r)
+    outs = []
+    for nbytes in ("0", "65536"):
+        monkeypatch.setenv("MGPCG_TAIL_BYTES", nbytes)
+        p = mg.Problem(dims, mg_dtype=dtype, colour_order=order)
+        z = host(p.vcycle(dev(r)))
+        np.testing.assert_array_equal(z, ref)
+        x, h, its, st = p.solve(dev(r), max_iters=25)
+        assert st == mg.OK and p.check() == mg.OK
+        outs.append((host(x), h.copy()))
+        p.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
