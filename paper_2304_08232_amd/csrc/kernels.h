@@ -20,7 +20,8 @@ uint32_t standard_zs_mask(int k, int order);
 // one colour pass of the coloured Gauss-Seidel smoother; mode: plain,
 // zero start, or with the restriction / refinement of the level fused in
 // (`coarse` is then the coarse-level rc or zc)
-enum { kPassPlain = 0, kPassZeroStart = 1, kPassRestrict = 2, kPassProlong = 3 };
+enum { kPassPlain = 0, kPassZeroStart = 1, kPassRestrict = 2, kPassProlong = 3, kPassTwice = 4,
+       kPassTwiceZeroStart = 5, kPassZeroStart01 = 6 };
 template <typename T>
 hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
                        const int *done, T *coarse, hipStream_t s);

@@ -85,10 +85,9 @@ struct Base27 {
 // the dependent gathers, so a wave keeps 54 streaming loads and then 27
 // gathers in flight.
 template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
-__device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_t *__restrict__ col,
-                                         const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
-                                         const T *x, int v, T (&a)[kW], T (&xv)[kW]) {
-    int32_t c[kW];
+__device__ __forceinline__ void load_slots(const T *__restrict__ val, const int32_t *__restrict__ col,
+                                           const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
+                                           T (&a)[kW], int32_t (&c)[kW]) {
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
         const bool sk = (SKIP >> s) & 1u;
@@ -96,11 +95,25 @@ __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_
         if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb[s] + (int32_t)ld<NT>(dcol + (int64_t)s * n + i));
         else c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
     }
+}
+
+template <typename T, int R, uint32_t SKIP>
+__device__ __forceinline__ void gather_slots(const T *x, int v, const T (&a)[kW], const int32_t (&c)[kW],
+                                             T (&xv)[kW]) {
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
         const bool sk = (SKIP >> s) & 1u;
         xv[s] = (!sk && a[s] != T(0)) ? x[(int64_t)c[s] * R + v] : T(0);
     }
+}
+
+template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
+__device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_t *__restrict__ col,
+                                         const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
+                                         const T *x, int v, T (&a)[kW], T (&xv)[kW]) {
+    int32_t c[kW];
+    load_slots<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, a, c);
+    gather_slots<T, R, SKIP>(x, v, a, c, xv);
 }
 
 // sum_j a_ij x_j over the 27 slots of row i, in slot order (ascending natural
@@ -336,19 +349,23 @@ template hipError_t launch_spmv<float>(const mgpcg_problem *, int, const float *
 // The update of one (row, rhs) of the pass; shared by the per-pass kernel
 // and the persistent coarse-level kernel.  inj_base is the first row of the
 // colour (the injection rows start there in MODE 1/2).
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, class SB>
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, class SB, bool TWICE = false>
 __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb,
                                          const T *__restrict__ r, T *z, int64_t i, int v, int64_t inj_base,
                                          T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
     const int64_t o = i * R + v;
+    // operator stream first; the transfer map and the coarse value travel
+    // with the gathers, so none of them adds a round trip of its own
+    T a[kW], xv[kW];
+    int32_t c[kW];
+    load_slots<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, a, c);
     const T rv = r[o];
-    T zc = T(0);
     int64_t co = 0;
     if (MODE != 0) co = (int64_t)inj_coarse[i - inj_base] * R + v;
+    gather_slots<T, R, SKIP>(z, v, a, c, xv);
+    T zc = T(0);
     if (MODE == 2) zc = coarse[co];
-    T a[kW], xv[kW];
-    load_row<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, z, v, a, xv);
     const T d = a[kCentre];
     // z_i before this pass (refined in MODE 2); 0 on a zero start
     const T zi = SKIP ? T(0) : (MODE == 2 ? xv[kCentre] + zc : xv[kCentre]);
@@ -360,6 +377,18 @@ __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, c
         if (!sk && a[s] != T(0)) acc = acc + a[s] * xv[s];
     }
     const T znew = (rv - acc + zi * d) / d;
+    if constexpr (TWICE) {
+        // the same colour again (the first pass of the backward sweep right
+        // after the last pass of the forward sweep): same neighbours, the new
+        // z_i on the diagonal, the full row in slot order
+        xv[kCentre] = znew;
+        T acc2 = 0;
+#pragma unroll
+        for (int s = 0; s < kW; ++s)
+            if (a[s] != T(0)) acc2 = acc2 + a[s] * xv[s];
+        z[o] = (rv - acc2 + znew * d) / d;
+        return;
+    }
     z[o] = znew;
     if (MODE == 1) {
         xv[kCentre] = znew;
@@ -371,7 +400,7 @@ __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, c
     }
 }
 
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8>
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, bool TWICE = false>
 __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
                                                  const Base27 sb,
@@ -395,7 +424,78 @@ __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict_
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
     if (rl >= count) return;
     if (done && done[grid * R + v]) return;
-    pass_row<T, R, SKIP, NT, MODE, D8>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse, inj_coarse);
+    pass_row<T, R, SKIP, NT, MODE, D8, Base27, TWICE>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse,
+                                                     inj_coarse);
+}
+
+// The first two passes of a zero-start forward sweep in one launch.  Colour
+// 0 reads no neighbour (z_i = (r_i - 0 + 0*d_i)/d_i); colour 1 reads only its
+// colour-0 neighbours, whose values this kernel forms on the fly with the
+// same expression instead of waiting for them.  Rows [coff0, coff2) hold both
+// colours contiguously (colour-major layout).
+template <typename T, int R, bool NT, bool D8, int ORD>
+__global__ __launch_bounds__(kBlock) void k_pass_zs01(int64_t n, const T *__restrict__ val,
+                                                      const int32_t *__restrict__ col,
+                                                      const int8_t *__restrict__ dcol, const Base27 sb1,
+                                                      const T *__restrict__ r, T *__restrict__ z,
+                                                      const Seg *__restrict__ tab, int64_t coff0, int64_t coff1,
+                                                      int64_t coff2, const int *__restrict__ done) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t row0, count;
+    int grid;
+    if (tab) {
+        const Seg e = tab[b];
+        row0 = e.row0;
+        count = e.count;
+        grid = e.grid;
+    } else {
+        row0 = coff0 + (int64_t)b * (kBlock / R);
+        count = coff2 - row0;
+        grid = 0;
+    }
+    const int rl = threadIdx.x / R, v = threadIdx.x % R;
+    if (rl >= count) return;
+    if (done && done[grid * R + v]) return;
+    const int64_t i = row0 + rl;
+    const int64_t o = i * R + v;
+    const T rv = r[o];
+    if (i < coff1) {
+        const T d = ld<NT>(val + (int64_t)kCentre * n + i);
+        const T acc = T(0), zi = T(0);
+        z[o] = (rv - acc + zi * d) / d;
+        return;
+    }
+    constexpr uint32_t SKIP = zs_mask(1, ORD);
+    T a[kW];
+    int32_t c[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
+        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb1[s] + (int32_t)ld<NT>(dcol + (int64_t)s * n + i));
+        else c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
+    }
+    T rj[kW], dj[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        const bool use = !sk && a[s] != T(0);
+        rj[s] = use ? r[(int64_t)c[s] * R + v] : T(0);
+        dj[s] = use ? val[(int64_t)kCentre * n + c[s]] : T(1);
+    }
+    const T d = a[kCentre];
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        if (!sk && a[s] != T(0)) {
+            const T acc0 = T(0), z0 = T(0);
+            const T zj = (rj[s] - acc0 + z0 * dj[s]) / dj[s];  // the colour-0 value of the first pass
+            acc = acc + a[s] * zj;
+        }
+    }
+    const T zi = T(0);
+    z[o] = (rv - acc + zi * d) / d;
 }
 
 template <typename T, int R, bool NT, bool D8>
@@ -418,6 +518,8 @@ static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T
 }
 
 uint32_t standard_zs_mask(int k, int order) { return zs_mask(k, order); }
+static_assert(zs_mask(7, 0) == (1u << kCentre) && zs_mask(7, 1) == (1u << kCentre),
+              "the last colour of a zero-start sweep reads every neighbour");
 
 template <typename T>
 hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
@@ -438,6 +540,59 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     const int32_t *ic = L.inj_coarse;
     Base27 sb;
     for (int t = 0; t < kW; ++t) sb.v[t] = L.dcol ? L.dbase_host[k * kW + t] : 0;
+    if (mode == kPassZeroStart01) {
+        if (k != 0 || !L.zs_std || L.ncol != 8 || (R != 1 && R != 16)) return hipErrorInvalidValue;
+        int cnt01;
+        const Seg *tab01 = nullptr;
+        if (P->G > 1) {
+            tab01 = L.pass_tab + L.pass_first[0];
+            cnt01 = L.pass_first[2] - L.pass_first[0];
+        } else {
+            cnt01 = (int)((L.coff[2] - L.coff[0] + kBlock / R - 1) / (kBlock / R));
+        }
+        Base27 sb1;
+        for (int t = 0; t < kW; ++t) sb1.v[t] = L.dcol ? L.dbase_host[1 * kW + t] : 0;
+#define MG_ZS01(RR, NT, D8)                                                                             \
+    if (P->colour_order)                                                                               \
+        k_pass_zs01<T, RR, NT, D8, 1><<<cnt01, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
+                                                            L.coff[0], L.coff[1], L.coff[2], done);      \
+    else                                                                                               \
+        k_pass_zs01<T, RR, NT, D8, 0><<<cnt01, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
+                                                            L.coff[0], L.coff[1], L.coff[2], done);
+#define MG_ZS01_R(NT, D8)                                                                               \
+    if (R == 1) { MG_ZS01(1, NT, D8) } else { MG_ZS01(16, NT, D8) }
+        if (L.stream_nt) {
+            if (L.dcol) { MG_ZS01_R(true, true) } else { MG_ZS01_R(true, false) }
+        } else {
+            if (L.dcol) { MG_ZS01_R(false, true) } else { MG_ZS01_R(false, false) }
+        }
+#undef MG_ZS01_R
+#undef MG_ZS01
+        return hipGetLastError();
+    }
+    if (mode == kPassTwice || mode == kPassTwiceZeroStart) {
+        // colour k swept twice in a row; on a zero start its first update
+        // skips only the diagonal (every other colour is already written)
+        if (mode == kPassTwiceZeroStart && (!L.zs_std || k != L.ncol - 1 || L.ncol != 8)) return hipErrorInvalidValue;
+#define MG_TWICE_LAUNCH(SKIPM, NT, D8)                                                                  \
+    MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, \
+                                                                                tab, rb, re, done, nullptr, \
+                                                                                nullptr)));
+#define MG_TWICE_MODE(SKIPM)                                                                            \
+    if (L.stream_nt) {                                                                                 \
+        if (L.dcol) { MG_TWICE_LAUNCH(SKIPM, true, true) } else { MG_TWICE_LAUNCH(SKIPM, true, false) }    \
+    } else {                                                                                           \
+        if (L.dcol) { MG_TWICE_LAUNCH(SKIPM, false, true) } else { MG_TWICE_LAUNCH(SKIPM, false, false) }  \
+    }
+        if (mode == kPassTwiceZeroStart) {
+            MG_TWICE_MODE(zs_mask(7, 0))
+        } else {
+            MG_TWICE_MODE(0u)
+        }
+#undef MG_TWICE_MODE
+#undef MG_TWICE_LAUNCH
+        return hipGetLastError();
+    }
     if (mode == kPassZeroStart) {
         if (!L.zs_std || (R != 1 && R != 16)) return hipErrorInvalidValue;
         const int ord = P->colour_order;
@@ -535,7 +690,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned *flags, int B, unsigned ep
     return s_ok != 0;
 }
 
-template <typename T, int R, bool D8, uint32_t SKIP, int MODE>
+template <typename T, int R, bool D8, uint32_t SKIP, int MODE, bool TWICE = false>
 __device__ __forceinline__ void coarse_phase(const CoarseLevel &lv, int k, T *coarse, int bid, int B) {
     const int32_t *sb = D8 ? lv.dbase + k * kW : nullptr;
     const int64_t r0 = lv.coff[k], r1 = lv.coff[k + 1];
@@ -544,8 +699,9 @@ __device__ __forceinline__ void coarse_phase(const CoarseLevel &lv, int k, T *co
     for (int64_t base = r0 + (int64_t)bid * rpb; base < r1; base += (int64_t)B * rpb) {
         const int64_t i = base + rl;
         if (i < r1)
-            pass_row<T, R, SKIP, false, MODE, D8>(lv.n, (const T *)lv.val, lv.col, lv.dcol, sb, (const T *)lv.r,
-                                                 (T *)lv.z, i, v, r0, coarse, lv.inj_coarse);
+            pass_row<T, R, SKIP, false, MODE, D8, const int32_t *, TWICE>(
+                lv.n, (const T *)lv.val, lv.col, lv.dcol, sb, (const T *)lv.r, (T *)lv.z, i, v, r0, coarse,
+                lv.inj_coarse);
     }
 }
 
@@ -611,6 +767,12 @@ __device__ __forceinline__ void coarse_run_phase(const CoarseArgs &A, int ph, in
         case kOpProlong:
             coarse_prolong<T, R>(lv, (const T *)A.lev[l + 1].z, bid, B);
             break;
+        case kOpTwice:
+            coarse_phase<T, R, D8, 0u, 0, true>(lv, k, nullptr, bid, B);
+            break;
+        case kOpTwiceZeroStart:
+            coarse_phase<T, R, D8, zs_mask(7, ORD), 0, true>(lv, k, nullptr, bid, B);
+            break;
         default:
             break;
     }
@@ -663,9 +825,14 @@ __global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *
                                                       i, 0, 0, nullptr, nullptr);                      \
     __syncthreads();
     MG_TAIL_FWD(0) MG_TAIL_FWD(1) MG_TAIL_FWD(2) MG_TAIL_FWD(3)
-    MG_TAIL_FWD(4) MG_TAIL_FWD(5) MG_TAIL_FWD(6) MG_TAIL_FWD(7)
+    MG_TAIL_FWD(4) MG_TAIL_FWD(5) MG_TAIL_FWD(6)
 #undef MG_TAIL_FWD
-    for (int k = 7; k >= 0; --k) {
+    // colour 7: the last forward and the first backward pass in one
+    for (int64_t i = ct.coff[7] + threadIdx.x; i < ct.coff[8]; i += kTailBlock)
+        pass_row<T, 1, zs_mask(7, ORD), false, 0, D8, const int32_t *, true>(
+            n, val, col, dcol, D8 ? dbase + 7 * kW : nullptr, rs, zs, i, 0, 0, nullptr, nullptr);
+    __syncthreads();
+    for (int k = 6; k >= 0; --k) {
         for (int64_t i = ct.coff[k] + threadIdx.x; i < ct.coff[k + 1]; i += kTailBlock)
             pass_row<T, 1, 0u, false, 0, D8>(n, val, col, dcol, D8 ? dbase + k * kW : nullptr, rs, zs, i, 0, 0,
                                              nullptr, nullptr);

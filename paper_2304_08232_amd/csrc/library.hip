@@ -425,8 +425,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             for (int l = from; l < L; ++l) {
                 const bool coarser = l + 1 < L;
                 const bool fuse = coarser && P->lev[l].fuse_transfers;
-                for (int k = 0; k < 8; ++k) ph(l, k, kOpZeroStart);
-                for (int k = 7; k >= 1; --k) ph(l, k, kOpPlain);
+                for (int k = 0; k < 7; ++k) ph(l, k, kOpZeroStart);
+                ph(l, 7, kOpTwiceZeroStart);
+                for (int k = 6; k >= 1; --k) ph(l, k, kOpPlain);
                 ph(l, 0, fuse ? kOpFusedRestrict : kOpPlain);
                 if (coarser && !fuse) ph(l, 0, kOpRestrict);
             }
@@ -434,8 +435,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
                 const bool fuse = P->lev[l].fuse_transfers;
                 if (!fuse) ph(l, 0, kOpProlong);
                 ph(l, 0, fuse ? kOpFusedProlong : kOpPlain);
-                for (int k = 1; k < 8; ++k) ph(l, k, kOpPlain);
-                for (int k = 7; k >= 0; --k) ph(l, k, kOpPlain);
+                for (int k = 1; k < 7; ++k) ph(l, k, kOpPlain);
+                ph(l, 7, kOpTwice);
+                for (int k = 6; k >= 0; --k) ph(l, k, kOpPlain);
             }
             if ((int)prog.size() > kMaxPhases) return false;
             memset(&A, 0, sizeof(A));
@@ -547,12 +549,23 @@ template <typename T>
 hipError_t sweep(const mgpcg_problem *P, int l, const T *val, const T *r, T *z, int first_mode,
                  int last_mode, T *coarse, const int *done, hipStream_t s) {
     const Level &Lv = P->lev[l];
+    const int c = Lv.ncol;
     hipError_t e;
-    for (int k = 0; k < Lv.ncol; ++k) {
-        const int mode = k == 0 ? first_mode : (first_mode == kPassZeroStart ? kPassZeroStart : kPassPlain);
+    // The last forward pass and the first backward pass update the same colour
+    // c-1 back to back with unchanged neighbours: one kernel applies both
+    // updates (same arithmetic, one read of the rows).
+    const bool zs = first_mode == kPassZeroStart;
+    const bool twice = c >= 2 && (!zs || (Lv.zs_std && c == 8 && (P->R == 1 || P->R == 16)));
+    // a zero start also folds the trivial first pass into the second
+    const bool zs01 = zs && twice && c == 8;
+    for (int k = 0; k < c; ++k) {
+        int mode = k == 0 ? first_mode : (zs ? kPassZeroStart : kPassPlain);
+        if (k == c - 1 && twice) mode = zs ? kPassTwiceZeroStart : kPassTwice;
+        if (zs01 && k == 0) mode = kPassZeroStart01;
+        if (zs01 && k == 1) continue;
         if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s)) != hipSuccess) return e;
     }
-    for (int k = Lv.ncol - 1; k >= 0; --k) {
+    for (int k = (twice ? c - 2 : c - 1); k >= 0; --k) {
         const int mode = k == 0 ? last_mode : kPassPlain;
         if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s)) != hipSuccess) return e;
     }

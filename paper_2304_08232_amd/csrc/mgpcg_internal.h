@@ -103,7 +103,7 @@ struct CoarseLevel {
 // operations of the persistent coarse-level kernel's phase program; a phase
 // is level | colour << 4 | op << 8
 enum CoarseOp { kOpPlain = 0, kOpZeroStart = 1, kOpFusedRestrict = 2, kOpFusedProlong = 3,
-                kOpRestrict = 4, kOpProlong = 5 };
+                kOpRestrict = 4, kOpProlong = 5, kOpTwice = 6, kOpTwiceZeroStart = 7 };
 constexpr int kMaxPhases = 320;
 struct CoarseArgs {
     CoarseLevel lev[MGPCG_MAX_LEVELS];
