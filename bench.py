@@ -223,6 +223,10 @@ def main():
     t_launch, launches = dominant_kernel(torch, mg, prob)
     log(f"dominant kernel: {t_launch * 1e6:.2f} us per colour pass over {launches} launches")
     if args.only_kernel:
+        # three eager iterations, so that counter runs also see the CG kernels
+        prob.set_graph_mode(False)
+        prob.solve(prob.make_rhs_ones(layout=mg.INTERNAL), max_iters=3, layout=mg.INTERNAL)
+        torch.cuda.synchronize()
         # calibration for the HBM counters: one copy of exactly 512 MiB
         src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

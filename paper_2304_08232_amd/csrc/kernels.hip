@@ -91,9 +91,9 @@ __device__ __forceinline__ void load_slots(const T *__restrict__ val, const int3
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
         const bool sk = (SKIP >> s) & 1u;
-        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
-        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb[s] + (int32_t)ld<NT>(dcol + (int64_t)s * n + i));
-        else c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
+        a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
+        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb[s] + (int32_t)ld<NT>(dcol + ell_index(s, i)));
+        else c[s] = sk ? 0 : ld<NT>(col + ell_index(s, i));
     }
 }
 
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_build_ell(
         bool in = jx >= 0 && jx < nx && jy >= 0 && jy < ny && jz >= 0 && jz < nz;
         double v = in ? (s == kCentre ? d : -1.0) : 0.0;
         int32_t c = in ? perm[natoff[g] + jx + (int64_t)nx * (jy + (int64_t)ny * jz)] : (int32_t)i;
-        int64_t e = (int64_t)s * n + i;
+        int64_t e = ell_index(s, i);
         if (val64) val64[e] = v;
         if (val32) val32[e] = (float)v;
         if (col) col[e] = c;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_delta_encode(int64_t n, const double
     const int k = colour_of(coff, ncol, i);
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
-        const int64_t e = (int64_t)s * n + i;
+        const int64_t e = ell_index(s, i);
         const bool real = val64 ? val64[e] != 0.0 : val32[e] != 0.0f;
         int64_t dlt = real ? (int64_t)col[e] - i - base[k * kW + s] : 0;
         if (dlt < -128 || dlt > 127) {
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_zs01(int64_t n, const T *__rest
     const int64_t o = i * R + v;
     const T rv = r[o];
     if (i < coff1) {
-        const T d = ld<NT>(val + (int64_t)kCentre * n + i);
+        const T d = ld<NT>(val + ell_index(kCentre, i));
         const T acc = T(0), zi = T(0);
         z[o] = (rv - acc + zi * d) / d;
         return;
@@ -471,9 +471,9 @@ __global__ __launch_bounds__(kBlock) void k_pass_zs01(int64_t n, const T *__rest
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
         const bool sk = (SKIP >> s) & 1u;
-        a[s] = (!sk || s == kCentre) ? ld<NT>(val + (int64_t)s * n + i) : T(0);
-        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb1[s] + (int32_t)ld<NT>(dcol + (int64_t)s * n + i));
-        else c[s] = sk ? 0 : ld<NT>(col + (int64_t)s * n + i);
+        a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
+        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb1[s] + (int32_t)ld<NT>(dcol + ell_index(s, i)));
+        else c[s] = sk ? 0 : ld<NT>(col + ell_index(s, i));
     }
     T rj[kW], dj[kW];
 #pragma unroll
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_zs01(int64_t n, const T *__rest
         const bool sk = (SKIP >> s) & 1u;
         const bool use = !sk && a[s] != T(0);
         rj[s] = use ? r[(int64_t)c[s] * R + v] : T(0);
-        dj[s] = use ? val[(int64_t)kCentre * n + c[s]] : T(1);
+        dj[s] = use ? val[ell_index(kCentre, c[s])] : T(1);
     }
     const T d = a[kCentre];
     T acc = 0;

@@ -152,7 +152,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         }
         Lv.coff[Lv.ncol] = off;
         if (off != Lv.n) return fail(MGPCG_ERR_DIMS, "internal: colour classes do not cover the grid");
-        if (Lv.n * kW >= ((int64_t)1 << 31) || Lv.n * R >= ((int64_t)1 << 31))
+        if (ell_size(Lv.n) >= ((int64_t)1 << 31) || Lv.n * R >= ((int64_t)1 << 31))
             return fail(MGPCG_ERR_DIMS, "problem too large for 32-bit row indices");
 
         // permutation natural packed -> internal
@@ -316,9 +316,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
     const bool fp32 = P->mg_dtype == MGPCG_FP32;
     for (int l = 0; l < L; ++l) {
         Level &Lv = P->lev[l];
-        if (l == 0 || !fp32) ST_TRY(dalloc(&Lv.val64, Lv.n * kW));
-        if (fp32) ST_TRY(dalloc(&Lv.val32, Lv.n * kW));
-        ST_TRY(dalloc(&Lv.col, Lv.n * kW));
+        if (l == 0 || !fp32) ST_TRY(dalloc(&Lv.val64, ell_size(Lv.n)));
+        if (fp32) ST_TRY(dalloc(&Lv.val32, ell_size(Lv.n)));
+        ST_TRY(dalloc(&Lv.col, ell_size(Lv.n)));
         if (fp32) {
             float *r32, *z32;
             ST_TRY(dalloc(&r32, Lv.n * R));
@@ -335,7 +335,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         HIP_TRY(launch_build_ell(P, l, theta, s));
         if (Lv.dbase) {
             // try the compact column format; keep int32 columns if any delta is out of range
-            ST_TRY(dalloc(&Lv.dcol, Lv.n * kW));
+            ST_TRY(dalloc(&Lv.dcol, ell_size(Lv.n)));
             int64_t *coff_dev = nullptr;
             int *bad = nullptr;
             std::vector<int64_t> coffv(Lv.coff.begin(), Lv.coff.end());
@@ -358,7 +358,12 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
     }
 
     // level-0 reduction tables: grid by grid, chunks of kBlock/R rows (one
-    // per thread) and of kVecRows*kBlock/R rows
+    // per thread) and of kVecRows*kBlock/R rows.  The workgroups of the
+    // one-row table gather from all colours, so its chunks are ordered slab
+    // by slab (the j-th eighth of every colour, then the next eighth): the
+    // contiguous block range an XCD receives is then one spatial slab, whose
+    // gathers stay in that XCD's L2, instead of one colour that needs
+    // neighbours from the whole grid.
     {
         const Level &L0 = P->lev[0];
         int64_t max_blocks = 0;
@@ -366,17 +371,22 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             std::vector<Seg> tab;
             std::vector<int> gb(G + 1, 0);
             const int rows = (t == 0 ? 1 : kVecRows) * kBlock / R;
+            const int slabs = t == 0 ? 8 : 1;
             for (int g = 0; g < G; ++g) {
                 gb[g] = (int)tab.size();
                 const LevelGrid &lg = L0.grids[g];
-                for (int k = 0; k < L0.ncol; ++k)
-                    for (int64_t a = 0; a < lg.seg_len[k]; a += rows) {
-                        Seg e;
-                        e.row0 = lg.seg_off[k] + a;
-                        e.count = (int32_t)std::min<int64_t>(rows, lg.seg_len[k] - a);
-                        e.grid = (int16_t)g;
-                        e.colour = (int16_t)k;
-                        tab.push_back(e);
+                for (int j = 0; j < slabs; ++j)
+                    for (int k = 0; k < L0.ncol; ++k) {
+                        const int64_t nch = (lg.seg_len[k] + rows - 1) / rows;
+                        for (int64_t c = nch * j / slabs; c < nch * (j + 1) / slabs; ++c) {
+                            const int64_t a = c * rows;
+                            Seg e;
+                            e.row0 = lg.seg_off[k] + a;
+                            e.count = (int32_t)std::min<int64_t>(rows, lg.seg_len[k] - a);
+                            e.grid = (int16_t)g;
+                            e.colour = (int16_t)k;
+                            tab.push_back(e);
+                        }
                     }
             }
             gb[G] = (int)tab.size();

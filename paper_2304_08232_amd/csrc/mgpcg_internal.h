@@ -29,6 +29,17 @@ constexpr int kCentre = 13;   // slot of the diagonal
 constexpr int kBlock = 256;   // threads per workgroup
 constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
 
+// Operator storage (ELL-27, blocked by wavefront): rows are grouped in blocks
+// of 64; a block holds its 27 slots one after another, each as 64 consecutive
+// entries.  Slot s of row i is at ell_index(s, i).  A wavefront of 64
+// consecutive rows therefore reads its whole operator from one contiguous
+// run, and each of its slot loads is 64 consecutive entries.
+constexpr int kEllRows = 64;
+__host__ __device__ inline int64_t ell_index(int64_t s, int64_t i) {
+    return (i / kEllRows) * (kW * kEllRows) + s * kEllRows + (i % kEllRows);
+}
+inline int64_t ell_size(int64_t n) { return (n + kEllRows - 1) / kEllRows * kEllRows * kW; }
+
 // One workgroup's share of rows: [row0, row0+count), all in grid `grid`.
 struct Seg {
     int64_t row0;
