@@ -241,7 +241,8 @@ def main():
     hist = np.zeros(ITERS)
     its = np.zeros(1, np.int32)
     st = mg.mgpcg_solve_result(prob.h, ITERS, hist, its)
-    log(f"solve: {t_step * 1e3:.3f} ms per 50 iterations, relres[50] = {hist[-1]:.6e}, status {st}")
+    log(f"solve: {t_step * 1e3:.3f} ms per 50 iterations, relres[50] = {hist[-1]:.6e}, iterations {int(its[0])}, "
+        f"status {st}")
     # practical ceiling: a plain device copy of 1 GiB (torch), read + write bytes
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)

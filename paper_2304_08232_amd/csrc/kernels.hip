@@ -401,7 +401,7 @@ __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, c
 }
 
 template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, bool TWICE = false>
-__global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict__ val,
+__global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
                                                  const Base27 sb,
                                                  const T *__restrict__ r, T *z,
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict_
         count = e.count;
         grid = e.grid;
     } else {
-        row0 = row_base + (int64_t)b * (kBlock / R);
+        row0 = row_base + (int64_t)b * (pass_block(NT) / R);
         count = row_end - row0;
         grid = 0;
     }
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(int64_t n, const T *__restrict_
 // same expression instead of waiting for them.  Rows [coff0, coff2) hold both
 // colours contiguously (colour-major layout).
 template <typename T, int R, bool NT, bool D8, int ORD>
-__global__ __launch_bounds__(kBlock) void k_pass_zs01(int64_t n, const T *__restrict__ val,
+__global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T *__restrict__ val,
                                                       const int32_t *__restrict__ col,
                                                       const int8_t *__restrict__ dcol, const Base27 sb1,
                                                       const T *__restrict__ r, T *__restrict__ z,
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_zs01(int64_t n, const T *__rest
         count = e.count;
         grid = e.grid;
     } else {
-        row0 = coff0 + (int64_t)b * (kBlock / R);
+        row0 = coff0 + (int64_t)b * (pass_block(NT) / R);
         count = coff2 - row0;
         grid = 0;
     }
@@ -504,7 +504,7 @@ static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T
                     int64_t re, const int *done) {
 #define MG_ZS_CASE(K, O)                                                                              \
     case K + 8 * O:                                                                                   \
-        k_pass<T, R, zs_mask(K, O), NT, 0, D8><<<cnt, kBlock, 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
+        k_pass<T, R, zs_mask(K, O), NT, 0, D8><<<cnt, pass_block(NT), 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
                                                                       done, nullptr, nullptr);      \
         break;
     switch (k + 8 * order) {
@@ -534,7 +534,8 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         cnt = L.pass_first[k + 1] - first;
         tab = L.pass_tab + first;
     } else {
-        cnt = (int)((re - rb + kBlock / R - 1) / (kBlock / R));
+        const int rows = pass_block(L.stream_nt) / R;
+        cnt = (int)((re - rb + rows - 1) / rows);
     }
     if (cnt == 0) return hipSuccess;
     const int32_t *ic = L.inj_coarse;
@@ -548,16 +549,17 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
             tab01 = L.pass_tab + L.pass_first[0];
             cnt01 = L.pass_first[2] - L.pass_first[0];
         } else {
-            cnt01 = (int)((L.coff[2] - L.coff[0] + kBlock / R - 1) / (kBlock / R));
+            const int rows = pass_block(L.stream_nt) / R;
+            cnt01 = (int)((L.coff[2] - L.coff[0] + rows - 1) / rows);
         }
         Base27 sb1;
         for (int t = 0; t < kW; ++t) sb1.v[t] = L.dcol ? L.dbase_host[1 * kW + t] : 0;
 #define MG_ZS01(RR, NT, D8)                                                                             \
     if (P->colour_order)                                                                               \
-        k_pass_zs01<T, RR, NT, D8, 1><<<cnt01, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
+        k_pass_zs01<T, RR, NT, D8, 1><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
                                                             L.coff[0], L.coff[1], L.coff[2], done);      \
     else                                                                                               \
-        k_pass_zs01<T, RR, NT, D8, 0><<<cnt01, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
+        k_pass_zs01<T, RR, NT, D8, 0><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
                                                             L.coff[0], L.coff[1], L.coff[2], done);
 #define MG_ZS01_R(NT, D8)                                                                               \
     if (R == 1) { MG_ZS01(1, NT, D8) } else { MG_ZS01(16, NT, D8) }
@@ -575,7 +577,7 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         // skips only the diagonal (every other colour is already written)
         if (mode == kPassTwiceZeroStart && (!L.zs_std || k != L.ncol - 1 || L.ncol != 8)) return hipErrorInvalidValue;
 #define MG_TWICE_LAUNCH(SKIPM, NT, D8)                                                                  \
-    MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, \
+    MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, \
                                                                                 tab, rb, re, done, nullptr, \
                                                                                 nullptr)));
 #define MG_TWICE_MODE(SKIPM)                                                                            \
@@ -608,7 +610,7 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         return hipGetLastError();
     }
 #define MG_PASS_LAUNCH(NT, M, D8)                                                                      \
-    MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, D8><<<cnt, kBlock, 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, tab, \
+    MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, D8><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, tab, \
                                                                       rb, re, done, coarse, ic)));
 #define MG_PASS_MODE(M)                                                                                \
     if (L.stream_nt) {                                                                                 \

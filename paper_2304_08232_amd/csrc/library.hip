@@ -207,10 +207,14 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             Lv.dbase_host = base;
         }
 
-        // colour-pass tables: one workgroup per kBlock/R rows, grid-homogeneous
+        const int64_t opbytes = Lv.n * kW * ((P->mg_dtype == MGPCG_FP32 && l > 0 ? 4 : 8) + 4);
+        int64_t nt_bytes = (int64_t)128 << 20;  // operators above half the Infinity Cache are streamed
+        if (const char *env = getenv("MGPCG_NT_BYTES")) nt_bytes = atoll(env);  // tuning override
+        Lv.stream_nt = opbytes > nt_bytes;
+        // colour-pass tables: one workgroup per pass_block/R rows, grid-homogeneous
         std::vector<Seg> tab;
         Lv.pass_first.assign(Lv.ncol + 1, 0);
-        const int rows_per_block = kBlock / R;
+        const int rows_per_block = pass_block(Lv.stream_nt) / R;
         for (int k = 0; k < Lv.ncol; ++k) {
             Lv.pass_first[k] = (int)tab.size();
             for (int g = 0; g < G; ++g) {
@@ -263,10 +267,6 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         Lv.zs_std = Lv.zs_ok && Lv.ncol == 8;
         for (int k = 0; k < Lv.ncol && Lv.zs_std; ++k)
             if (Lv.zi_skip[k] != standard_zs_mask(k, P->colour_order)) Lv.zs_std = false;
-        const int64_t opbytes = Lv.n * kW * ((P->mg_dtype == MGPCG_FP32 && l > 0 ? 4 : 8) + 4);
-        int64_t nt_bytes = (int64_t)128 << 20;  // operators above half the Infinity Cache are streamed
-        if (const char *env = getenv("MGPCG_NT_BYTES")) nt_bytes = atoll(env);  // tuning override
-        Lv.stream_nt = opbytes > nt_bytes;
         if (G > 1) {
             std::vector<int32_t> gon(Lv.n);
             for (int g = 0; g < G; ++g)
@@ -727,14 +727,17 @@ mgpcg_status fetch_result(mgpcg_problem *P, int max_iters, double *history_host,
     std::vector<int> iters(S), status(S);
     HIP_TRY(hipMemcpyAsync(iters.data(), P->sc.iter, S * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(status.data(), P->sc.status, S * sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<double> hist;
     if (history_host && max_iters > 0) {
         if (max_iters > P->hist_cap) return fail(MGPCG_ERR_INVALID_ARG, "max_iters exceeds the last solve's");
-        HIP_TRY(hipMemcpy2DAsync(history_host, (size_t)max_iters * sizeof(double), P->hist,
-                                 (size_t)P->hist_cap * sizeof(double), (size_t)max_iters * sizeof(double),
-                                 S, hipMemcpyDeviceToHost, s));
+        hist.resize((size_t)S * P->hist_cap);
+        HIP_TRY(hipMemcpyAsync(hist.data(), P->hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     if (iters_host) memcpy(iters_host, iters.data(), S * sizeof(int));
+    for (int i = 0; i < S && !hist.empty(); ++i)
+        memcpy(history_host + (size_t)i * max_iters, hist.data() + (size_t)i * P->hist_cap,
+               (size_t)max_iters * sizeof(double));
     bool breakdown = false, unconverged = false;
     for (int i = 0; i < S; ++i) {
         if (status[i] == MGPCG_ERR_BREAKDOWN) breakdown = true;

@@ -28,6 +28,10 @@ constexpr int kW = 27;        // ELL width (3x3x3 stencil)
 constexpr int kCentre = 13;   // slot of the diagonal
 constexpr int kBlock = 256;   // threads per workgroup
 constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
+// Workgroup size of a colour pass: 256 threads on streamed (large) levels;
+// one wavefront on cache-resident levels, whose passes are latency-bound, so
+// that their few rows are spread over as many CUs as possible.
+constexpr int pass_block(bool streamed) { return streamed ? 256 : 64; }
 
 // Operator storage (ELL-27, blocked by wavefront): rows are grouped in blocks
 // of 64; a block holds its 27 slots one after another, each as 64 consecutive
