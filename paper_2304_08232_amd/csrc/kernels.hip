@@ -79,22 +79,78 @@ struct Base27 {
     __device__ __forceinline__ int32_t operator[](int s) const { return v[s]; }
 };
 
-// Operator values a[s] and gathered x values xv[s] of the 27 slots of row i
-// (0 for padding slots and for slots in the compile-time SKIP mask).  All
-// value and column (or column-delta) loads of the row are issued first, then
-// the dependent gathers, so a wave keeps 54 streaming loads and then 27
-// gathers in flight.
+// The stored operator of one row, as loaded: the 27 values (0 for padding
+// slots and for slots in a compile-time SKIP mask) and the column data in
+// storage form (packed 8-bit deltas, or 32-bit columns).  Keeping the raw
+// words lets a load be in flight across a barrier: nothing uses them until
+// the columns are decoded.
+template <typename T, bool D8>
+struct RawRow {
+    T a[kW];
+    uint32_t w[D8 ? kDeltaWords : kW];
+};
+
+template <uint32_t SKIP, int q>
+constexpr bool word_needed() {
+    // a word of deltas is needed if any of its real slots is read
+    return ((~SKIP >> (4 * q)) & 0xFu & ((1u << (kW - 4 * q < 4 ? kW - 4 * q : 4)) - 1u)) != 0u;
+}
+
+template <typename T, uint32_t SKIP, bool NT, bool D8>
+__device__ __forceinline__ void load_raw(const T *__restrict__ val, const int32_t *__restrict__ col,
+                                         const int8_t *__restrict__ dcol, int64_t i, RawRow<T, D8> &rw) {
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        rw.a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
+    }
+    if constexpr (D8) {
+        const uint32_t *dw = (const uint32_t *)dcol;
+#define MG_LOAD_WORD(q) rw.w[q] = word_needed<SKIP, q>() ? ld<NT>(dw + delta_word(q, i)) : 0u;
+        MG_LOAD_WORD(0) MG_LOAD_WORD(1) MG_LOAD_WORD(2) MG_LOAD_WORD(3)
+        MG_LOAD_WORD(4) MG_LOAD_WORD(5) MG_LOAD_WORD(6)
+#undef MG_LOAD_WORD
+    } else {
+#pragma unroll
+        for (int s = 0; s < kW; ++s) {
+            const bool sk = (SKIP >> s) & 1u;
+            rw.w[s] = sk ? 0u : (uint32_t)ld<NT>(col + ell_index(s, i));
+        }
+    }
+}
+
+// absolute column of slot s of row i
+template <bool D8, typename T, class SB>
+__device__ __forceinline__ int32_t slot_col(const RawRow<T, D8> &rw, const SB &sb, int64_t i, int s) {
+    if constexpr (D8) {
+        const int32_t dl = (int32_t)(rw.w[s / 4] << (24 - 8 * (s % 4))) >> 24;  // sign-extended byte
+        return (int32_t)(i + sb[s] + dl);
+    } else {
+        return (int32_t)rw.w[s];
+    }
+}
+
+// absolute columns of the row (0 for skipped slots)
+template <uint32_t SKIP, bool D8, typename T, class SB>
+__device__ __forceinline__ void decode_cols(const RawRow<T, D8> &rw, const SB &sb, int64_t i, int32_t (&c)[kW]) {
+#pragma unroll
+    for (int s = 0; s < kW; ++s) c[s] = ((SKIP >> s) & 1u) ? 0 : slot_col<D8>(rw, sb, i, s);
+}
+
+// Operator values a[s] and absolute columns c[s] of the 27 slots of row i.
+// All value and column loads of the row are issued before anything uses
+// them, so a wave keeps 34 streaming loads (27 with 32-bit columns: 54) in
+// flight, and then its 27 gathers.
 template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
 __device__ __forceinline__ void load_slots(const T *__restrict__ val, const int32_t *__restrict__ col,
                                            const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
                                            T (&a)[kW], int32_t (&c)[kW]) {
+    (void)n;
+    RawRow<T, D8> rw;
+    load_raw<T, SKIP, NT, D8>(val, col, dcol, i, rw);
 #pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
-        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb[s] + (int32_t)ld<NT>(dcol + ell_index(s, i)));
-        else c[s] = sk ? 0 : ld<NT>(col + ell_index(s, i));
-    }
+    for (int s = 0; s < kW; ++s) a[s] = rw.a[s];
+    decode_cols<SKIP, D8>(rw, sb, i, c);
 }
 
 template <typename T, int R, uint32_t SKIP>
@@ -231,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_delta_encode(int64_t n, const double
             atomicOr(bad, 1);
             dlt = 0;
         }
-        dcol[e] = (int8_t)dlt;
+        dcol[4 * delta_word(s / 4, i) + s % 4] = (int8_t)dlt;
     }
 }
 
@@ -327,6 +383,44 @@ template hipError_t launch_spmv<float>(const mgpcg_problem *, int, const float *
 
 // ------------------------------------------------------------ colour pass
 
+// sum_s a[s] x(s) in slot order over the real slots not in SKIP; x(s) is the
+// neighbour value of slot s (gathered into registers, or read from LDS)
+// (CHUNK < 27: x fetches its values CHUNK slots at a time through
+// x.load(first slot), which bounds the registers they occupy; the sum is
+// the same)
+template <typename T, uint32_t SKIP, int CHUNK = kW, class X>
+__device__ __forceinline__ T row_dot(const T (&a)[kW], X &x) {
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        if constexpr (CHUNK < kW)
+            if (s % CHUNK == 0) x.load(s);
+        const bool sk = (SKIP >> s) & 1u;
+        if (!sk && a[s] != T(0)) acc = acc + a[s] * x(s);
+        if constexpr (CHUNK < kW)
+            if (s % CHUNK == CHUNK - 1 || s == kW - 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// Gauss-Seidel update of one row (Eq. (1) in the masked-product form of
+// Sec. III-A): z_i = (r_i - sum_j a_ij z_j + z_i d_i) / d_i, where the sum
+// runs over the whole row including the diagonal (x(kCentre) = z_i, or
+// skipped on a zero start).
+template <typename T, uint32_t SKIP, int CHUNK = kW, class X>
+__device__ __forceinline__ T gs_update(const T (&a)[kW], X &&x, T rv, T zi) {
+    const T d = a[kCentre];
+    return (rv - row_dot<T, SKIP, CHUNK>(a, x) + zi * d) / d;
+}
+
+// The same colour once more (first pass of the backward sweep right after
+// the last pass of the forward sweep): same neighbours, the new z_i on the
+// diagonal, the full row in slot order.
+template <typename T, class X>
+__device__ __forceinline__ T gs_again(const T (&a)[kW], const X &x, T rv, T znew) {
+    return gs_update<T, 0u>(a, [&](int s) { return s == kCentre ? znew : x(s); }, rv, znew);
+}
+
 // One colour of the coloured Gauss-Seidel pass (Listing 3 of the paper, the
 // masked product and the update fused).  Rows of one colour are independent,
 // so the update is done in place: a row reads only other colours and itself.
@@ -366,37 +460,19 @@ __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, c
     gather_slots<T, R, SKIP>(z, v, a, c, xv);
     T zc = T(0);
     if (MODE == 2) zc = coarse[co];
-    const T d = a[kCentre];
     // z_i before this pass (refined in MODE 2); 0 on a zero start
     const T zi = SKIP ? T(0) : (MODE == 2 ? xv[kCentre] + zc : xv[kCentre]);
     if (MODE == 2) xv[kCentre] = zi;
-    T acc = 0;
-#pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        if (!sk && a[s] != T(0)) acc = acc + a[s] * xv[s];
-    }
-    const T znew = (rv - acc + zi * d) / d;
+    const auto x = [&](int s) { return xv[s]; };
+    const T znew = gs_update<T, SKIP>(a, x, rv, zi);
     if constexpr (TWICE) {
-        // the same colour again (the first pass of the backward sweep right
-        // after the last pass of the forward sweep): same neighbours, the new
-        // z_i on the diagonal, the full row in slot order
-        xv[kCentre] = znew;
-        T acc2 = 0;
-#pragma unroll
-        for (int s = 0; s < kW; ++s)
-            if (a[s] != T(0)) acc2 = acc2 + a[s] * xv[s];
-        z[o] = (rv - acc2 + znew * d) / d;
+        z[o] = gs_again(a, x, rv, znew);
         return;
     }
     z[o] = znew;
     if (MODE == 1) {
         xv[kCentre] = znew;
-        T f = 0;
-#pragma unroll
-        for (int s = 0; s < kW; ++s)
-            if (a[s] != T(0)) f = f + a[s] * xv[s];
-        coarse[co] = rv - f;
+        coarse[co] = rv - row_dot<T, 0u>(a, x);
     }
 }
 
@@ -468,13 +544,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
     constexpr uint32_t SKIP = zs_mask(1, ORD);
     T a[kW];
     int32_t c[kW];
-#pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
-        if constexpr (D8) c[s] = sk ? 0 : (int32_t)(i + sb1[s] + (int32_t)ld<NT>(dcol + ell_index(s, i)));
-        else c[s] = sk ? 0 : ld<NT>(col + ell_index(s, i));
-    }
+    load_slots<T, R, SKIP, NT, D8>(val, col, dcol, sb1, n, i, a, c);
     T rj[kW], dj[kW];
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
@@ -805,10 +875,85 @@ __global__ __launch_bounds__(kBlock) void k_coarse_vcycle(CoarseArgs A) {
 }
 
 // Coarsest level, one workgroup: its symmetric sweep (zero-start forward
-// pass, backward pass) with r and z held in LDS.  The 16 colour passes are
+// pass, backward pass) with r and z held in LDS.  The 15 colour passes are
 // separated by workgroup barriers instead of kernel launches, and the 27
-// gathers of every row read LDS; only the operator rows come from memory.
-constexpr int kTailBlock = 512;
+// gathers of every row read LDS.  The operator rows do not depend on z, so
+// the pass is software-pipelined: while one pass computes, each thread's row
+// of the next pass is already on its way from memory into registers, and
+// the barriers between passes wait for LDS traffic only.
+
+// barrier for LDS data only: prefetches from global memory stay in flight
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename T, bool D8, uint32_t SKIP>
+__device__ __forceinline__ void tail_load(const T *__restrict__ val, const int32_t *__restrict__ col,
+                                          const int8_t *__restrict__ dcol, const CoffTable &ct, int k,
+                                          RawRow<T, D8> &rw) {
+    // unconditional (threads past the colour's end load its last row, or
+    // row 0), so that the loads are straight-line code the wait counters
+    // track exactly
+    int64_t i = ct.coff[k] + threadIdx.x;
+    if (i >= ct.coff[k + 1]) i = ct.coff[k + 1] > 0 ? ct.coff[k + 1] - 1 : 0;
+    load_raw<T, SKIP, false, D8>(val, col, dcol, i, rw);
+    // keep the loads here: without this the compiler sinks them to their
+    // use in the next pass, which would put them back on the critical path
+    asm volatile("" ::: "memory");
+}
+
+// the [8][27] column bases, read through the constant address space: scalar
+// loads, which neither wait behind the vector prefetches nor hold registers
+// between passes
+typedef const __attribute__((address_space(4))) int32_t *ConstBases;
+
+// Neighbour values of one row read from LDS nine slots at a time (the sums
+// call load() at the start of each group), the columns decoded from the raw
+// row as they are needed; optionally with the diagonal slot replaced by a
+// given value.
+template <typename T, bool D8, uint32_t SKIP, bool CENTRE>
+struct LdsGather {
+    const T *zs;
+    const RawRow<T, D8> &rw;
+    ConstBases cb;
+    int64_t i;
+    T centre;
+    T buf[kW];
+    __device__ __forceinline__ void load(int s0) {
+        // unconditional reads (an unused slot reads row 0), so that the nine
+        // are issued together instead of one branch each
+#pragma unroll
+        for (int s = s0; s < s0 + 9 && s < kW; ++s) {
+            const bool use = !((SKIP >> s) & 1u) && rw.a[s] != T(0);
+            const T v = zs[use ? slot_col<D8>(rw, cb, i, s) : 0];
+            buf[s] = (CENTRE && s == kCentre) ? centre : (use ? v : T(0));
+        }
+    }
+    __device__ __forceinline__ T operator()(int s) const { return buf[s]; }
+};
+
+// one row of a pass with z in LDS (rows of one colour never neighbour each
+// other, so nothing a row reads changes during the pass)
+template <typename T, bool D8, uint32_t SKIP, bool TWICE>
+__device__ __forceinline__ void tail_row(const RawRow<T, D8> &rw, ConstBases cb, const T *rs, T *zs, int64_t i) {
+    const T rv = rs[i];
+    const T zi = SKIP ? T(0) : zs[slot_col<D8>(rw, cb, i, kCentre)];
+    const T znew = gs_update<T, SKIP, 9>(rw.a, LdsGather<T, D8, SKIP, false>{zs, rw, cb, i, T(0)}, rv, zi);
+    // a second pass of the same colour: the full row with the new diagonal value
+    zs[i] = TWICE ? gs_update<T, 0u, 9>(rw.a, LdsGather<T, D8, 0u, true>{zs, rw, cb, i, znew}, rv, znew) : znew;
+}
+
+// the rows of colour k (one per thread: the level qualifies only if every
+// colour fits in the workgroup), operators from the prefetched raw rows
+template <typename T, bool D8, uint32_t SKIP, bool TWICE>
+__device__ __forceinline__ void tail_pass(ConstBases cb, const CoffTable &ct, int k, const RawRow<T, D8> &rw,
+                                          const T *rs, T *zs) {
+    const int64_t i = ct.coff[k] + threadIdx.x;
+    if (i < ct.coff[k + 1]) tail_row<T, D8, SKIP, TWICE>(rw, cb + k * kW, rs, zs, i);
+}
+
 template <typename T, bool D8, int ORD>
 __global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *__restrict__ val,
                                                             const int32_t *__restrict__ col,
@@ -816,30 +961,37 @@ __global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *
                                                             const int32_t *__restrict__ dbase, CoffTable ct,
                                                             const T *__restrict__ r, T *__restrict__ z) {
     extern __shared__ char tail_lds[];
+    const ConstBases tb = (ConstBases)dbase;
     T *rs = (T *)tail_lds;
     T *zs = rs + n;
+    RawRow<T, D8> b0, b1;
+    tail_load<T, D8, zs_mask(0, ORD)>(val, col, dcol, ct, 0, b0);
     for (int64_t i = threadIdx.x; i < n; i += kTailBlock) rs[i] = r[i];
     __syncthreads();
-    // forward, zero start: colour k reads only colours < k
-#define MG_TAIL_FWD(K)                                                                                 \
-    for (int64_t i = ct.coff[K] + threadIdx.x; i < ct.coff[K + 1]; i += kTailBlock)                     \
-        pass_row<T, 1, zs_mask(K, ORD), false, 0, D8>(n, val, col, dcol, D8 ? dbase + K * kW : nullptr, rs, zs, \
-                                                      i, 0, 0, nullptr, nullptr);                      \
+    // forward, zero start (colour k reads only colours < k); colour 7 is the
+    // last forward and the first backward pass in one; then backward 6..0.
+    // Pass p computes from buffer p % 2 while buffer (p+1) % 2 is refilled.
+#define MG_TAIL_STEP(K, SK, TW, BC, KN, SKN, BN)                                                        \
+    tail_load<T, D8, SKN>(val, col, dcol, ct, KN, BN);                                                 \
+    tail_pass<T, D8, SK, TW>(tb, ct, K, BC, rs, zs);                                                   \
+    lds_barrier();
+    MG_TAIL_STEP(0, zs_mask(0, ORD), false, b0, 1, zs_mask(1, ORD), b1)
+    MG_TAIL_STEP(1, zs_mask(1, ORD), false, b1, 2, zs_mask(2, ORD), b0)
+    MG_TAIL_STEP(2, zs_mask(2, ORD), false, b0, 3, zs_mask(3, ORD), b1)
+    MG_TAIL_STEP(3, zs_mask(3, ORD), false, b1, 4, zs_mask(4, ORD), b0)
+    MG_TAIL_STEP(4, zs_mask(4, ORD), false, b0, 5, zs_mask(5, ORD), b1)
+    MG_TAIL_STEP(5, zs_mask(5, ORD), false, b1, 6, zs_mask(6, ORD), b0)
+    MG_TAIL_STEP(6, zs_mask(6, ORD), false, b0, 7, zs_mask(7, ORD), b1)
+    MG_TAIL_STEP(7, zs_mask(7, ORD), true, b1, 6, 0u, b0)
+    MG_TAIL_STEP(6, 0u, false, b0, 5, 0u, b1)
+    MG_TAIL_STEP(5, 0u, false, b1, 4, 0u, b0)
+    MG_TAIL_STEP(4, 0u, false, b0, 3, 0u, b1)
+    MG_TAIL_STEP(3, 0u, false, b1, 2, 0u, b0)
+    MG_TAIL_STEP(2, 0u, false, b0, 1, 0u, b1)
+    MG_TAIL_STEP(1, 0u, false, b1, 0, 0u, b0)
+#undef MG_TAIL_STEP
+    tail_pass<T, D8, 0u, false>(tb, ct, 0, b0, rs, zs);
     __syncthreads();
-    MG_TAIL_FWD(0) MG_TAIL_FWD(1) MG_TAIL_FWD(2) MG_TAIL_FWD(3)
-    MG_TAIL_FWD(4) MG_TAIL_FWD(5) MG_TAIL_FWD(6)
-#undef MG_TAIL_FWD
-    // colour 7: the last forward and the first backward pass in one
-    for (int64_t i = ct.coff[7] + threadIdx.x; i < ct.coff[8]; i += kTailBlock)
-        pass_row<T, 1, zs_mask(7, ORD), false, 0, D8, const int32_t *, true>(
-            n, val, col, dcol, D8 ? dbase + 7 * kW : nullptr, rs, zs, i, 0, 0, nullptr, nullptr);
-    __syncthreads();
-    for (int k = 6; k >= 0; --k) {
-        for (int64_t i = ct.coff[k] + threadIdx.x; i < ct.coff[k + 1]; i += kTailBlock)
-            pass_row<T, 1, 0u, false, 0, D8>(n, val, col, dcol, D8 ? dbase + k * kW : nullptr, rs, zs, i, 0, 0,
-                                             nullptr, nullptr);
-        __syncthreads();
-    }
     for (int64_t i = threadIdx.x; i < n; i += kTailBlock) z[i] = zs[i];
 }
 

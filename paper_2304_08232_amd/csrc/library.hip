@@ -335,7 +335,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         HIP_TRY(launch_build_ell(P, l, theta, s));
         if (Lv.dbase) {
             // try the compact column format; keep int32 columns if any delta is out of range
-            ST_TRY(dalloc(&Lv.dcol, ell_size(Lv.n)));
+            ST_TRY(dalloc(&Lv.dcol, delta_bytes(Lv.n)));
             int64_t *coff_dev = nullptr;
             int *bad = nullptr;
             std::vector<int64_t> coffv(Lv.coff.begin(), Lv.coff.end());
@@ -511,8 +511,10 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         if (const char *env = getenv("MGPCG_TAIL_BYTES")) tail_bytes = atoll(env);  // tuning override
         const Level &Lt = P->lev[L - 1];
         const int64_t need = Lt.n * 2 * (fp32 ? 4 : 8);
+        bool fits = true;
+        for (int k = 0; k < Lt.ncol; ++k) fits = fits && Lt.coff[k + 1] - Lt.coff[k] <= kTailBlock;
         P->tail_ok = L >= 2 && R == 1 && Lt.zs_std && Lt.ncol == 8 && need <= tail_bytes &&
-                     need <= (64 << 10);
+                     need <= (64 << 10) && fits;
         P->tail_lw = P->tail_ok ? L - 1 : L;
     }
     HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int), hipHostMallocDefault));

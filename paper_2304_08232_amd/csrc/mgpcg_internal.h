@@ -32,6 +32,9 @@ constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
 // one wavefront on cache-resident levels, whose passes are latency-bound, so
 // that their few rows are spread over as many CUs as possible.
 constexpr int pass_block(bool streamed) { return streamed ? 256 : 64; }
+// threads of the single-workgroup coarsest-level kernel; it is used only when
+// every colour of that level has at most this many rows
+constexpr int kTailBlock = 512;
 
 // Operator storage (ELL-27, blocked by wavefront): rows are grouped in blocks
 // of 64; a block holds its 27 slots one after another, each as 64 consecutive
@@ -43,6 +46,14 @@ __host__ __device__ inline int64_t ell_index(int64_t s, int64_t i) {
     return (i / kEllRows) * (kW * kEllRows) + s * kEllRows + (i % kEllRows);
 }
 inline int64_t ell_size(int64_t n) { return (n + kEllRows - 1) / kEllRows * kEllRows * kW; }
+// Delta-coded columns: four 8-bit deltas per 32-bit word, blocked like the
+// values.  Word delta_word(q, i) holds slots 4q..4q+3 of row i, slot s in
+// byte s % 4, so a row's 27 deltas are 7 coalesced word loads.
+constexpr int kDeltaWords = (kW + 3) / 4;
+__host__ __device__ inline int64_t delta_word(int64_t q, int64_t i) {
+    return (i / kEllRows) * (kDeltaWords * kEllRows) + q * kEllRows + (i % kEllRows);
+}
+inline int64_t delta_bytes(int64_t n) { return (n + kEllRows - 1) / kEllRows * kEllRows * kDeltaWords * 4; }
 
 // One workgroup's share of rows: [row0, row0+count), all in grid `grid`.
 struct Seg {
@@ -68,12 +79,13 @@ struct Level {
     std::vector<LevelGrid> grids;
     std::vector<int64_t> coff;  // ncol+1: internal row range of each colour (all grids)
 
-    double *val64 = nullptr;  // [27][n], FP64 operator (level 0 always; all levels if FP64 V-cycle)
-    float *val32 = nullptr;   // [27][n], FP32 operator (FP32 V-cycle)
-    int32_t *col = nullptr;   // [27][n] absolute columns (NULL when delta-coded)
-    // delta-coded columns: col(i,s) = i + dbase[colour(i)*27 + s] + dcol[s*n+i];
+    double *val64 = nullptr;  // at ell_index(s, i): FP64 operator (level 0 always; all levels if FP64 V-cycle)
+    float *val32 = nullptr;   // at ell_index(s, i): FP32 operator (FP32 V-cycle)
+    int32_t *col = nullptr;   // at ell_index(s, i): absolute columns (NULL when delta-coded)
+    // delta-coded columns: col(i,s) = i + dbase[colour(i)*27 + s] + delta(s, i),
+    // the deltas packed four to a word at delta_word(s / 4, i), byte s % 4;
     // used when every real entry's delta fits in int8 (single-grid problems)
-    int8_t *dcol = nullptr;   // [27][n]
+    int8_t *dcol = nullptr;
     int32_t *dbase = nullptr; // [8][27]
     std::vector<int32_t> dbase_host;
     int32_t *perm = nullptr;  // natural packed row -> internal row
