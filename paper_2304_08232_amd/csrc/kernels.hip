@@ -398,7 +398,7 @@ __device__ __forceinline__ T row_dot(const T (&a)[kW], X &x) {
         const bool sk = (SKIP >> s) & 1u;
         if (!sk && a[s] != T(0)) acc = acc + a[s] * x(s);
         if constexpr (CHUNK < kW)
-            if (s % CHUNK == CHUNK - 1 || s == kW - 1) __builtin_amdgcn_sched_barrier(0);
+            if (s % CHUNK == CHUNK - 1 || s == kW - 1) asm volatile("" ::: "memory");
     }
     return acc;
 }
@@ -890,14 +890,17 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 template <typename T, bool D8, uint32_t SKIP>
-__device__ __forceinline__ void tail_load(const T *__restrict__ val, const int32_t *__restrict__ col,
-                                          const int8_t *__restrict__ dcol, const CoffTable &ct, int k,
+__device__ __forceinline__ void tail_load(const T *val, const int32_t *col, const int8_t *dcol, const CoffTable &ct,
+                                          int k,
                                           RawRow<T, D8> &rw) {
     // unconditional (threads past the colour's end load its last row, or
     // row 0), so that the loads are straight-line code the wait counters
     // track exactly
     int64_t i = ct.coff[k] + threadIdx.x;
     if (i >= ct.coff[k + 1]) i = ct.coff[k + 1] > 0 ? ct.coff[k + 1] - 1 : 0;
+    // an opaque copy of the row index per pass: the compiler can then not
+    // merge these loads with the other sweep's loads of the same colour
+    asm volatile("" : "+v"(i));
     load_raw<T, SKIP, false, D8>(val, col, dcol, i, rw);
     // keep the loads here: without this the compiler sinks them to their
     // use in the next pass, which would put them back on the critical path
@@ -954,10 +957,12 @@ __device__ __forceinline__ void tail_pass(ConstBases cb, const CoffTable &ct, in
     if (i < ct.coff[k + 1]) tail_row<T, D8, SKIP, TWICE>(rw, cb + k * kW, rs, zs, i);
 }
 
+// (the operator pointers are deliberately not __restrict__: that lets the
+// compiler keep the forward sweep's loads of a colour for its backward pass,
+// which does not fit in registers next to the prefetch buffers)
 template <typename T, bool D8, int ORD>
-__global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *__restrict__ val,
-                                                            const int32_t *__restrict__ col,
-                                                            const int8_t *__restrict__ dcol,
+__global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *val, const int32_t *col,
+                                                            const int8_t *dcol,
                                                             const int32_t *__restrict__ dbase, CoffTable ct,
                                                             const T *__restrict__ r, T *__restrict__ z) {
     extern __shared__ char tail_lds[];
