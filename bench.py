@@ -18,7 +18,6 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extensions]
        [--no-cpu-baseline] [--only-kernel]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,19 +38,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "library.hip", "kernels.h", "mgpcg_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2304_08232_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(per_launch_alg_bytes):
     """HBM bytes per launch of the dominant kernel from the committed PMC
     summary, if it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "pass_l0_128cubed_traffic.json")
     if not os.path.exists(path):
         return None
+    from paper_2304_08232_amd.profsummary import kernel_source_hash
     d = json.load(open(path))
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
@@ -88,22 +81,24 @@ def time_to_tol(torch, prob, b, tol, max_iters=1000, reps=3):
     return best, out
 
 
-def dominant_kernel(torch, mg, prob, reps=20):
-    """Average duration of one level-0 colour pass (k_pass) from HIP events
-    recorded on the stream the library launches on."""
+def dominant_kernel(torch, mg, prob, reps=40):
+    """Average duration of the level-0 colour pass kernel (k_pass, plain mode)
+    from HIP events recorded on the stream the library launches it on: the
+    eight colour passes, `reps` times over, one launch each."""
     n = prob.n(0)
     r = torch.rand(n, dtype=torch.float64, device="cuda")
     z = torch.rand(n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
-    for _ in range(3):
+    for _ in range(3):  # warm-up; also puts the host ahead of the device
         mg.mgpcg_gs_sweep(prob.h, 0, r, z, layout=mg.INTERNAL, stream=stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        mg.mgpcg_gs_sweep(prob.h, 0, r, z, layout=mg.INTERNAL, stream=stream)
+        for k in range(8):
+            mg.mgpcg_colour_pass(prob.h, 0, k, r, z, layout=mg.INTERNAL, stream=stream)
     e1.record(stream)
     e1.synchronize()
-    launches = reps * 16
+    launches = reps * 8
     return e0.elapsed_time(e1) * 1e-3 / launches, launches
 
 
@@ -271,7 +266,7 @@ def main():
         "us_per_iteration": round(t_step / ITERS * 1e6, 2),
         "final_relres": float(hist[-1]),
         "stream_copy_gbs": round(copy_gbs, 1),
-        "roofline": {"bound": "hbm", "kernel": "k_pass<double,1,false> (level-0 colour pass)",
+        "roofline": {"bound": "hbm", "kernel": "k_pass<double, 1, 0u, true, 0, true, false> (level-0 colour pass)",
                      "achieved": round(achieved, 1), "peak": perfmodel.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / perfmodel.HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(per_launch_bytes),

@@ -120,6 +120,17 @@ mgpcg_status mgpcg_make_rhs_ones(const mgpcg_problem *p, double *b, int layout, 
 mgpcg_status mgpcg_gs_sweep(const mgpcg_problem *p, int level, const double *r, double *z, int layout,
                             hipStream_t stream);
 
+/* Sec. III-A, Listings 2-3: one colour pass of the coloured Gauss-Seidel
+ * smoother at `level`, in place on z: for every row i of colour `colour`,
+ * z_i <- (r_i - sum_j a_ij z_j + z_i a_ii) / a_ii, the sum over the whole row
+ * with z as it stands (rows of one colour are not coupled, so the order
+ * within the colour does not matter).  Colours are numbered as the greedy
+ * colouring finds them (reversed under colour_order 1); a 3-D grid with every
+ * extent >= 2 has 8.  Runs in the V-cycle precision.  r and z must not
+ * overlap.  MGPCG_ERR_INVALID_ARG if colour is not a colour of the level. */
+mgpcg_status mgpcg_colour_pass(const mgpcg_problem *p, int level, int colour, const double *r, double *z,
+                               int layout, hipStream_t stream);
+
 /* Sec. II-D Listing 1 and Sec. II-F: rc = inject(r - A_l z), the residual at
  * the injection points (2jx, 2jy, 2jz) of level `level` written to level+1.
  * V-cycle precision.  Requires level+1 < levels. */

@@ -944,6 +944,23 @@ mgpcg_status mgpcg_gs_sweep(const mgpcg_problem *p_, int level, const double *r,
     });
 }
 
+mgpcg_status mgpcg_colour_pass(const mgpcg_problem *p_, int level, int colour, const double *r, double *z,
+                               int layout, hipStream_t s) {
+    ST_TRY(check_level(p_, level));
+    ST_TRY(check_layout(layout));
+    if (!r || !z) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    if (colour < 0 || colour >= p_->lev[level].ncol) return fail(MGPCG_ERR_INVALID_ARG, "no such colour at this level");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    DeviceGuard dg(p->device);
+    return with_level_vectors(p, level, r, z, layout, s, true, [&](const void *rv, void *zv) {
+        if (p->mg_dtype == MGPCG_FP64)
+            return launch_pass<double>(p, level, colour, kPassPlain, p->lev[level].val64, (const double *)rv,
+                                       (double *)zv, nullptr, (double *)nullptr, s);
+        return launch_pass<float>(p, level, colour, kPassPlain, p->lev[level].val32, (const float *)rv, (float *)zv,
+                                  nullptr, (float *)nullptr, s);
+    });
+}
+
 mgpcg_status mgpcg_restrict(const mgpcg_problem *p_, int level, const double *r, const double *z, double *rc,
                             int layout, hipStream_t s) {
     ST_TRY(check_level(p_, level, true));

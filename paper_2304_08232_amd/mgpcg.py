@@ -23,7 +23,8 @@ OK, NOT_CONVERGED, ERR_BREAKDOWN = 0, 1, -5
 # every function declared in include/mgpcg.h
 ABI_FUNCTIONS = [
     "mgpcg_create", "mgpcg_destroy", "mgpcg_info", "mgpcg_set_theta", "mgpcg_to_internal",
-    "mgpcg_to_natural", "mgpcg_spmv", "mgpcg_make_rhs_ones", "mgpcg_gs_sweep", "mgpcg_restrict",
+    "mgpcg_to_natural", "mgpcg_spmv", "mgpcg_make_rhs_ones", "mgpcg_gs_sweep", "mgpcg_colour_pass",
+    "mgpcg_restrict",
     "mgpcg_prolong_add", "mgpcg_mg_vcycle", "mgpcg_pcg_solve", "mgpcg_solve_result",
     "mgpcg_theta_grad", "mgpcg_set_graph_mode", "mgpcg_set_coarse_mode", "mgpcg_check",
     "mgpcg_last_error",
@@ -67,6 +68,7 @@ def lib():
         L.mgpcg_spmv.argtypes = [vp, i32, vp, vp, i32, vp]
         L.mgpcg_make_rhs_ones.argtypes = [vp, vp, i32, vp]
         L.mgpcg_gs_sweep.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.mgpcg_colour_pass.argtypes = [vp, i32, i32, vp, vp, i32, vp]
         L.mgpcg_restrict.argtypes = [vp, i32, vp, vp, vp, i32, vp]
         L.mgpcg_prolong_add.argtypes = [vp, i32, vp, vp, i32, vp]
         L.mgpcg_mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
@@ -145,6 +147,11 @@ def mgpcg_make_rhs_ones(h, b, layout=NATURAL, stream=None):
 
 def mgpcg_gs_sweep(h, level, r, z, layout=NATURAL, stream=None):
     return _check(lib().mgpcg_gs_sweep(C.c_void_p(h), level, _ptr(r), _ptr(z), layout, _stream(stream)))
+
+
+def mgpcg_colour_pass(h, level, colour, r, z, layout=NATURAL, stream=None):
+    return _check(lib().mgpcg_colour_pass(C.c_void_p(h), level, colour, _ptr(r), _ptr(z), layout,
+                                          _stream(stream)))
 
 
 def mgpcg_restrict(h, level, r, z, rc, layout=NATURAL, stream=None):
@@ -264,6 +271,11 @@ class Problem:
     def gs_sweep(self, r, z, level=0, layout=NATURAL):
         z = z.clone()
         mgpcg_gs_sweep(self.h, level, r, z, layout)
+        return z
+
+    def colour_pass(self, r, z, colour, level=0, layout=NATURAL):
+        z = z.clone()
+        mgpcg_colour_pass(self.h, level, colour, r, z, layout)
         return z
 
     def restrict(self, r, z, level=0, layout=NATURAL):

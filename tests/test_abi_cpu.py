@@ -56,6 +56,7 @@ def test_argument_errors_without_device():
     n = C.c_int64()
     assert L.mgpcg_info(None, 0, C.byref(n), None, None) == -1
     assert L.mgpcg_spmv(None, 0, None, None, 0, None) == -1
+    assert L.mgpcg_colour_pass(None, 0, 0, None, None, 0, None) == -1
     assert L.mgpcg_pcg_solve(None, None, None, 10, C.c_double(0.0), None, None, 0, None) == -1
     assert L.mgpcg_last_error()
 

@@ -82,6 +82,10 @@ def test_kernels_bitwise_each_level(mg, dims, order):
         np.testing.assert_array_equal(host(p.spmv(dev(x), level=l)), o.spmv(x, level=l))
         # one symmetric coloured sweep from a nonzero z
         np.testing.assert_array_equal(host(p.gs_sweep(dev(x), dev(z0), level=l)), o.sgs(x, z0, level=l))
+        # each colour pass on its own (Listing 3), same colour numbering
+        for k in range(o.ncolours(l)):
+            np.testing.assert_array_equal(host(p.colour_pass(dev(x), dev(z0), k, level=l)),
+                                          o.colour_pass(k, x, z0, level=l))
         if l + 1 < 4:
             np.testing.assert_array_equal(host(p.restrict(dev(x), dev(z0), level=l)),
                                           o.restrict(x, z0, level=l))
@@ -199,6 +203,10 @@ def test_error_paths(mg):
         mg.mgpcg_spmv(p.h, 0, v, v, layout=7)
     with pytest.raises(mg.MGPCGError):
         mg.mgpcg_pcg_solve(p.h, v, v, -1)
+    for bad in (-1, 8):
+        with pytest.raises(mg.MGPCGError) as e:
+            mg.mgpcg_colour_pass(p.h, 0, bad, v, p.zeros())
+        assert e.value.status == -1
     with pytest.raises(mg.MGPCGError) as e:
         mg.Problem((12, 16, 16))
     assert e.value.status == -2
