@@ -96,14 +96,11 @@ constexpr bool word_needed() {
     return ((~SKIP >> (4 * q)) & 0xFu & ((1u << (kW - 4 * q < 4 ? kW - 4 * q : 4)) - 1u)) != 0u;
 }
 
+// The column data are loaded first: the gathers need only them (not the
+// values), so they can leave while the value loads are still streaming.
 template <typename T, uint32_t SKIP, bool NT, bool D8>
 __device__ __forceinline__ void load_raw(const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, int64_t i, RawRow<T, D8> &rw) {
-#pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        rw.a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
-    }
     if constexpr (D8) {
         const uint32_t *dw = (const uint32_t *)dcol;
 #define MG_LOAD_WORD(q) rw.w[q] = word_needed<SKIP, q>() ? ld<NT>(dw + delta_word(q, i)) : 0u;
@@ -116,6 +113,11 @@ __device__ __forceinline__ void load_raw(const T *__restrict__ val, const int32_
             const bool sk = (SKIP >> s) & 1u;
             rw.w[s] = sk ? 0u : (uint32_t)ld<NT>(col + ell_index(s, i));
         }
+    }
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        rw.a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
     }
 }
 
@@ -130,11 +132,20 @@ __device__ __forceinline__ int32_t slot_col(const RawRow<T, D8> &rw, const SB &s
     }
 }
 
-// absolute columns of the row (0 for skipped slots)
+// Absolute columns of the row (0 for skipped slots), each a valid row of the
+// level: a padding slot's delta-coded column (i + base) may fall outside
+// [0, n), so delta-coded columns are clamped.  Real columns are unchanged
+// by the clamp; a padding slot's gather then reads some valid row and its
+// value is never used (the sums skip slots whose value is 0).
 template <uint32_t SKIP, bool D8, typename T, class SB>
-__device__ __forceinline__ void decode_cols(const RawRow<T, D8> &rw, const SB &sb, int64_t i, int32_t (&c)[kW]) {
+__device__ __forceinline__ void decode_cols(const RawRow<T, D8> &rw, const SB &sb, int64_t n, int64_t i,
+                                            int32_t (&c)[kW]) {
 #pragma unroll
-    for (int s = 0; s < kW; ++s) c[s] = ((SKIP >> s) & 1u) ? 0 : slot_col<D8>(rw, sb, i, s);
+    for (int s = 0; s < kW; ++s) {
+        int32_t cs = ((SKIP >> s) & 1u) ? 0 : slot_col<D8>(rw, sb, i, s);
+        if constexpr (D8) cs = min(max(cs, 0), (int32_t)(n - 1));
+        c[s] = cs;
+    }
 }
 
 // Operator values a[s] and absolute columns c[s] of the 27 slots of row i.
@@ -145,21 +156,24 @@ template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
 __device__ __forceinline__ void load_slots(const T *__restrict__ val, const int32_t *__restrict__ col,
                                            const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
                                            T (&a)[kW], int32_t (&c)[kW]) {
-    (void)n;
     RawRow<T, D8> rw;
     load_raw<T, SKIP, NT, D8>(val, col, dcol, i, rw);
 #pragma unroll
     for (int s = 0; s < kW; ++s) a[s] = rw.a[s];
-    decode_cols<SKIP, D8>(rw, sb, i, c);
+    decode_cols<SKIP, D8>(rw, sb, n, i, c);
 }
 
+// x at the 27 columns (0 for skipped slots).  The gathers depend on the
+// columns only, not on the values: a padding slot gathers a valid row whose
+// value the sums ignore.
 template <typename T, int R, uint32_t SKIP>
 __device__ __forceinline__ void gather_slots(const T *x, int v, const T (&a)[kW], const int32_t (&c)[kW],
                                              T (&xv)[kW]) {
+    (void)a;
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
         const bool sk = (SKIP >> s) & 1u;
-        xv[s] = (!sk && a[s] != T(0)) ? x[(int64_t)c[s] * R + v] : T(0);
+        xv[s] = !sk ? x[(int64_t)c[s] * R + v] : T(0);
     }
 }
 
