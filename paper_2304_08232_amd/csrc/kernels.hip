@@ -177,6 +177,11 @@ __device__ __forceinline__ void gather_slots(const T *x, int v, const T (&a)[kW]
     }
 }
 
+// Operator values a[s] and x at the columns xv[s] of row i.  The column
+// words are loaded first and the gathers leave as soon as they arrive, while
+// the value loads are still streaming.  (Predicting the columns and gathering
+// together with the operator loads, with a check afterwards, was measured
+// slower on the latency-bound levels: ~4.45 against ~4.0 us per level-2 pass.)
 template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
 __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
@@ -456,22 +461,24 @@ __device__ __forceinline__ T gs_again(const T (&a)[kW], const X &x, T rv, T znew
 // otherwise workgroup b owns rows [row_base + b*rows, ...) of the colour.
 // The update of one (row, rhs) of the pass; shared by the per-pass kernel
 // and the persistent coarse-level kernel.  inj_base is the first row of the
-// colour (the injection rows start there in MODE 1/2).
+// colour (the injection rows start there in MODE 1/2).  dflag (may be NULL)
+// is the system's convergence flag: it is loaded with the operator and only
+// the stores wait for it, so a pass does not begin with a round trip.
 template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, class SB, bool TWICE = false>
 __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb,
                                          const T *__restrict__ r, T *z, int64_t i, int v, int64_t inj_base,
-                                         T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
+                                         T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
+                                         const int *__restrict__ dflag = nullptr) {
     const int64_t o = i * R + v;
-    // operator stream first; the transfer map and the coarse value travel
-    // with the gathers, so none of them adds a round trip of its own
-    T a[kW], xv[kW];
-    int32_t c[kW];
-    load_slots<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, a, c);
+    const int dv = dflag ? *dflag : 0;
+    // the transfer map and the coarse value travel with the operator loads
+    // and the gathers, so none of them adds a round trip of its own
     const T rv = r[o];
     int64_t co = 0;
     if (MODE != 0) co = (int64_t)inj_coarse[i - inj_base] * R + v;
-    gather_slots<T, R, SKIP>(z, v, a, c, xv);
+    T a[kW], xv[kW];
+    load_row<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, z, v, a, xv);
     T zc = T(0);
     if (MODE == 2) zc = coarse[co];
     // z_i before this pass (refined in MODE 2); 0 on a zero start
@@ -479,6 +486,7 @@ __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, c
     if (MODE == 2) xv[kCentre] = zi;
     const auto x = [&](int s) { return xv[s]; };
     const T znew = gs_update<T, SKIP>(a, x, rv, zi);
+    if (dv) return;  // converged system: leave its vectors alone
     if constexpr (TWICE) {
         z[o] = gs_again(a, x, rv, znew);
         return;
@@ -513,9 +521,11 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
     }
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
     if (rl >= count) return;
-    if (done && done[grid * R + v]) return;
+    // several grids: a converged grid is skipped before anything is loaded;
+    // one grid: its flag travels with the loads
+    if (tab && done && done[grid * R + v]) return;
     pass_row<T, R, SKIP, NT, MODE, D8, Base27, TWICE>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse,
-                                                     inj_coarse);
+                                                     inj_coarse, tab || !done ? nullptr : done + v);
 }
 
 // The first two passes of a zero-start forward sweep in one launch.  Colour
@@ -545,14 +555,15 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
     }
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
     if (rl >= count) return;
-    if (done && done[grid * R + v]) return;
+    if (tab && done && done[grid * R + v]) return;  // as in k_pass
+    const int dv = (!tab && done) ? done[v] : 0;
     const int64_t i = row0 + rl;
     const int64_t o = i * R + v;
     const T rv = r[o];
     if (i < coff1) {
         const T d = ld<NT>(val + ell_index(kCentre, i));
         const T acc = T(0), zi = T(0);
-        z[o] = (rv - acc + zi * d) / d;
+        if (!dv) z[o] = (rv - acc + zi * d) / d;
         return;
     }
     constexpr uint32_t SKIP = zs_mask(1, ORD);
@@ -579,7 +590,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
         }
     }
     const T zi = T(0);
-    z[o] = (rv - acc + zi * d) / d;
+    if (!dv) z[o] = (rv - acc + zi * d) / d;
 }
 
 template <typename T, int R, bool NT, bool D8>
@@ -1251,6 +1262,19 @@ __device__ __forceinline__ bool grid_done(const int *done, int g) {
     return all;
 }
 
+// Rows of one block of a vector kernel: from the segment table (several
+// grids), or, for one grid (tab == NULL), the blk-th chunk of `rows` rows of
+// [0, nrows), so that no table load precedes the data loads.
+__device__ __forceinline__ Seg vec_seg(const Seg *__restrict__ tab, int blk, int64_t nrows, int rows) {
+    if (tab) return tab[blk];
+    Seg e;
+    e.row0 = (int64_t)blk * rows;
+    e.count = (int32_t)(nrows - e.row0 < rows ? nrows - e.row0 : rows);
+    e.grid = 0;
+    e.colour = 0;
+    return e;
+}
+
 // r = b - A x, partial ||r||^2
 template <int R, bool D8>
 __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const double *__restrict__ val,
@@ -1278,13 +1302,14 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
 }
 
 // partial <r, z>
+// (done: NULL for one grid, whose converged state the finalize checks)
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_dot_rz(const double *__restrict__ r, const double *__restrict__ z,
-                                                   const Seg *__restrict__ tab, double *__restrict__ partials,
-                                                   const int *__restrict__ done) {
+                                                   const Seg *__restrict__ tab, int64_t nrows,
+                                                   double *__restrict__ partials, const int *__restrict__ done) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const Seg e = tab[blk];
-    if (grid_done<R>(done, e.grid)) return;
+    const Seg e = vec_seg(tab, blk, nrows, kVecRows * kBlock / R);
+    if (done && grid_done<R>(done, e.grid)) return;
     const int v = threadIdx.x % R;
     double acc = 0.0;
 #pragma unroll
@@ -1299,21 +1324,31 @@ __global__ __launch_bounds__(kBlock) void k_dot_rz(const double *__restrict__ r,
 }
 
 // p = z + beta p
+// (several grids: a converged grid's block returns before loading; the
+// flag of each system is otherwise checked only before the stores)
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ z, double *__restrict__ p,
-                                                     const Seg *__restrict__ tab, Scalars sc) {
-    const Seg e = tab[xcd_remap(blockIdx.x, gridDim.x)];
+                                                     const Seg *__restrict__ tab, int64_t nrows, Scalars sc) {
+    const Seg e = vec_seg(tab, xcd_remap(blockIdx.x, gridDim.x), nrows, kVecRows * kBlock / R);
     const int v = threadIdx.x % R;
     const int sys = e.grid * R + v;
-    if (sc.done[sys]) return;
+    if (tab && sc.done[sys]) return;
+    const int dn = sc.done[sys];
     const double beta = sc.beta[sys];
+    double pn[kVecRows];
 #pragma unroll
     for (int u = 0; u < kVecRows; ++u) {
         const int rl = threadIdx.x / R + u * (kBlock / R);
         if (rl < e.count) {
             const int64_t o = (e.row0 + rl) * R + v;
-            p[o] = z[o] + beta * p[o];
+            pn[u] = z[o] + beta * p[o];
         }
+    }
+    if (dn) return;
+#pragma unroll
+    for (int u = 0; u < kVecRows; ++u) {
+        const int rl = threadIdx.x / R + u * (kBlock / R);
+        if (rl < e.count) p[(e.row0 + rl) * R + v] = pn[u];
     }
 }
 
@@ -1328,7 +1363,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
                                                     const int *__restrict__ done) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const Seg e = tab[blk];
-    if (grid_done<R>(done, e.grid)) return;
+    if (done && grid_done<R>(done, e.grid)) return;  // done: NULL for one grid
     const int v = threadIdx.x % R, rl = threadIdx.x / R;
     double acc = 0.0;
     if (rl < e.count) {
@@ -1343,26 +1378,29 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
 }
 
 // x += alpha p; r -= alpha q; partial ||r||^2
+// (converged systems: as in k_update_p; their x and r are not written)
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, const double *__restrict__ p,
                                                       double *__restrict__ r, const double *__restrict__ q,
-                                                      const Seg *__restrict__ tab, double *__restrict__ partials,
-                                                      Scalars sc) {
+                                                      const Seg *__restrict__ tab, int64_t nrows,
+                                                      double *__restrict__ partials, Scalars sc) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const Seg e = tab[blk];
-    if (grid_done<R>(sc.done, e.grid)) return;
+    const Seg e = vec_seg(tab, blk, nrows, kVecRows * kBlock / R);
+    if (tab && grid_done<R>(sc.done, e.grid)) return;
     const int v = threadIdx.x % R;
     const int sys = e.grid * R + v;
+    const int dn = sc.done[sys];
+    const double alpha = sc.alpha[sys];
     double acc = 0.0;
-    if (!sc.done[sys]) {
-        const double alpha = sc.alpha[sys];
 #pragma unroll
-        for (int u = 0; u < kVecRows; ++u) {
-            const int rl = threadIdx.x / R + u * (kBlock / R);
-            if (rl < e.count) {
-                const int64_t o = (e.row0 + rl) * R + v;
-                x[o] = x[o] + alpha * p[o];
-                const double ri = r[o] - alpha * q[o];
+    for (int u = 0; u < kVecRows; ++u) {
+        const int rl = threadIdx.x / R + u * (kBlock / R);
+        if (rl < e.count) {
+            const int64_t o = (e.row0 + rl) * R + v;
+            const double xi = x[o] + alpha * p[o];
+            const double ri = r[o] - alpha * q[o];
+            if (!dn) {
+                x[o] = xi;
                 r[o] = ri;
                 acc += ri * ri;
             }
@@ -1464,14 +1502,18 @@ hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s) {
     return finalize<kInit>(P, 0, 0.0, 0, s);
 }
 hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s) {
-    MG_DISPATCH_R(P->R, (k_dot_rz<RR><<<P->n_red[1], kBlock, 0, s>>>(P->r, P->z, P->red_tab[1], P->sc.partials,
-                                                                     P->sc.done)));
+    const bool one = P->G == 1;
+    MG_DISPATCH_R(P->R, (k_dot_rz<RR><<<P->n_red[1], kBlock, 0, s>>>(P->r, P->z, one ? nullptr : P->red_tab[1],
+                                                                     P->lev[0].n, P->sc.partials,
+                                                                     one ? nullptr : P->sc.done)));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kRz>(P, 1, 0.0, 0, s);
 }
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s) {
-    MG_DISPATCH_R(P->R, (k_update_p<RR><<<P->n_red[1], kBlock, 0, s>>>(P->z, P->p, P->red_tab[1], P->sc)));
+    const bool one = P->G == 1;
+    MG_DISPATCH_R(P->R, (k_update_p<RR><<<P->n_red[1], kBlock, 0, s>>>(P->z, P->p, one ? nullptr : P->red_tab[1],
+                                                                       P->lev[0].n, P->sc)));
     return hipGetLastError();
 }
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
@@ -1479,18 +1521,20 @@ hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     if (L.dcol) {
         MG_DISPATCH_R(P->R, (k_spmv_pq<RR, true><<<P->n_red[0], kBlock, 0, s>>>(
                                 L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials,
-                                P->sc.done)));
+                                P->G == 1 ? nullptr : P->sc.done)));
     } else {
         MG_DISPATCH_R(P->R, (k_spmv_pq<RR, false><<<P->n_red[0], kBlock, 0, s>>>(
                                 L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials,
-                                P->sc.done)));
+                                P->G == 1 ? nullptr : P->sc.done)));
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kPq>(P, 0, 0.0, 0, s);
 }
 hipError_t launch_update_xr(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s) {
-    MG_DISPATCH_R(P->R, (k_update_xr<RR><<<P->n_red[1], kBlock, 0, s>>>(P->x, P->p, P->r, P->q, P->red_tab[1],
+    const bool one = P->G == 1;
+    MG_DISPATCH_R(P->R, (k_update_xr<RR><<<P->n_red[1], kBlock, 0, s>>>(P->x, P->p, P->r, P->q,
+                                                                        one ? nullptr : P->red_tab[1], P->lev[0].n,
                                                                         P->sc.partials, P->sc)));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -372,7 +372,20 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             std::vector<int> gb(G + 1, 0);
             const int rows = (t == 0 ? 1 : kVecRows) * kBlock / R;
             const int slabs = t == 0 ? 8 : 1;
-            for (int g = 0; g < G; ++g) {
+            if (t == 1 && G == 1) {
+                // one grid: the vector kernels take contiguous chunks of the
+                // whole vector and compute them from the block index
+                gb[0] = 0;
+                for (int64_t a = 0; a < L0.n; a += rows) {
+                    Seg e;
+                    e.row0 = a;
+                    e.count = (int32_t)std::min<int64_t>(rows, L0.n - a);
+                    e.grid = 0;
+                    e.colour = 0;
+                    tab.push_back(e);
+                }
+            }
+            for (int g = 0; g < G && !(t == 1 && G == 1); ++g) {
                 gb[g] = (int)tab.size();
                 const LevelGrid &lg = L0.grids[g];
                 for (int j = 0; j < slabs; ++j)
