@@ -22,9 +22,11 @@ uint32_t standard_zs_mask(int k, int order);
 // (`coarse` is then the coarse-level rc or zc)
 enum { kPassPlain = 0, kPassZeroStart = 1, kPassRestrict = 2, kPassProlong = 3, kPassTwice = 4,
        kPassTwiceZeroStart = 5, kPassZeroStart01 = 6 };
+// rzp (FP64, one grid, plain or double pass): the pass also writes one
+// partial of sum r_i z_i (its new z) per workgroup at rzp[block * R + rhs]
 template <typename T>
 hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
-                       const int *done, T *coarse, hipStream_t s);
+                       const int *done, T *coarse, hipStream_t s, double *rzp = nullptr);
 
 template <typename T>
 hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, const T *r, const T *z,
@@ -53,6 +55,7 @@ hipError_t launch_fill_u(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 // CG kernels on level 0 (FP64, internal layout), with per-system scalars
 hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s);
+hipError_t launch_finalize_rz(const mgpcg_problem *P, hipStream_t s);  // rho from the fused partials
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_update_xr(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s);

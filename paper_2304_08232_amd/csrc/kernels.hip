@@ -440,6 +440,32 @@ __device__ __forceinline__ T gs_again(const T (&a)[kW], const X &x, T rv, T znew
     return gs_update<T, 0u>(a, [&](int s) { return s == kCentre ? znew : x(s); }, rv, znew);
 }
 
+// wave-shuffle + LDS tree of per-rhs sums over a workgroup of BS threads;
+// thread v < R gets the total of rhs v
+template <int R, int BS = kBlock>
+__device__ __forceinline__ double block_sum(double acc, double *sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= R; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __syncthreads();
+    if (lane < R) sh[w * R + lane] = acc;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < R) {
+        t = sh[threadIdx.x];
+#pragma unroll
+        for (int k = 1; k < BS / 64; ++k) t += sh[k * R + threadIdx.x];
+    }
+    return t;
+}
+
+template <int R, int BS = kBlock>
+__device__ __forceinline__ void store_partial(double acc, int blk, double *partials) {
+    __shared__ double sh[(BS / 64) * R];
+    const double t = block_sum<R, BS>(acc, sh);
+    if (threadIdx.x < R) partials[(int64_t)blk * R + threadIdx.x] = t;
+}
+
 // One colour of the coloured Gauss-Seidel pass (Listing 3 of the paper, the
 // masked product and the update fused).  Rows of one colour are independent,
 // so the update is done in place: a row reads only other colours and itself.
@@ -464,8 +490,10 @@ __device__ __forceinline__ T gs_again(const T (&a)[kW], const X &x, T rv, T znew
 // colour (the injection rows start there in MODE 1/2).  dflag (may be NULL)
 // is the system's convergence flag: it is loaded with the operator and only
 // the stores wait for it, so a pass does not begin with a round trip.
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, class SB, bool TWICE = false>
-__device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
+// Returns r_i times the stored z_i when DOT (for <r, z>), else 0.
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, class SB, bool TWICE = false,
+          bool DOT = false>
+__device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb,
                                          const T *__restrict__ r, T *z, int64_t i, int v, int64_t inj_base,
                                          T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
@@ -486,26 +514,31 @@ __device__ __forceinline__ void pass_row(int64_t n, const T *__restrict__ val, c
     if (MODE == 2) xv[kCentre] = zi;
     const auto x = [&](int s) { return xv[s]; };
     const T znew = gs_update<T, SKIP>(a, x, rv, zi);
-    if (dv) return;  // converged system: leave its vectors alone
+    if (dv) return 0.0;  // converged system: leave its vectors alone
     if constexpr (TWICE) {
-        z[o] = gs_again(a, x, rv, znew);
-        return;
+        const T z2 = gs_again(a, x, rv, znew);
+        z[o] = z2;
+        return DOT ? (double)rv * (double)z2 : 0.0;
     }
     z[o] = znew;
     if (MODE == 1) {
         xv[kCentre] = znew;
         coarse[co] = rv - row_dot<T, 0u>(a, x);
     }
+    return DOT ? (double)rv * (double)znew : 0.0;
 }
 
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, bool TWICE = false>
+// DOT (one grid, no table): each workgroup also writes the sum of r_i z_i
+// over its rows to rzp[b * R + rhs].
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, bool TWICE = false, bool DOT = false>
 __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
                                                  const Base27 sb,
                                                  const T *__restrict__ r, T *z,
                                                  const Seg *__restrict__ tab, int64_t row_base,
                                                  int64_t row_end, const int *__restrict__ done,
-                                                 T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse) {
+                                                 T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
+                                                 double *__restrict__ rzp) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
@@ -520,12 +553,21 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
         grid = 0;
     }
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
-    if (rl >= count) return;
-    // several grids: a converged grid is skipped before anything is loaded;
-    // one grid: its flag travels with the loads
-    if (tab && done && done[grid * R + v]) return;
-    pass_row<T, R, SKIP, NT, MODE, D8, Base27, TWICE>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse,
-                                                     inj_coarse, tab || !done ? nullptr : done + v);
+    if constexpr (DOT) {
+        // every thread takes part in the workgroup's sum
+        double rz = 0.0;
+        if (rl < count)
+            rz = pass_row<T, R, SKIP, NT, MODE, D8, Base27, TWICE, true>(
+                n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse, inj_coarse, done ? done + v : nullptr);
+        store_partial<R, pass_block(NT)>(rz, b, rzp);
+    } else {
+        if (rl >= count) return;
+        // several grids: a converged grid is skipped before anything is
+        // loaded; one grid: its flag travels with the loads
+        if (tab && done && done[grid * R + v]) return;
+        pass_row<T, R, SKIP, NT, MODE, D8, Base27, TWICE>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base,
+                                                         coarse, inj_coarse, tab || !done ? nullptr : done + v);
+    }
 }
 
 // The first two passes of a zero-start forward sweep in one launch.  Colour
@@ -600,7 +642,7 @@ static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T
 #define MG_ZS_CASE(K, O)                                                                              \
     case K + 8 * O:                                                                                   \
         k_pass<T, R, zs_mask(K, O), NT, 0, D8><<<cnt, pass_block(NT), 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
-                                                                      done, nullptr, nullptr);      \
+                                                                      done, nullptr, nullptr, nullptr); \
         break;
     switch (k + 8 * order) {
         MG_ZS_CASE(0, 0) MG_ZS_CASE(1, 0) MG_ZS_CASE(2, 0) MG_ZS_CASE(3, 0)
@@ -618,9 +660,11 @@ static_assert(zs_mask(7, 0) == (1u << kCentre) && zs_mask(7, 1) == (1u << kCentr
 
 template <typename T>
 hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
-                       const int *done, T *coarse, hipStream_t s) {
+                       const int *done, T *coarse, hipStream_t s, double *rzp) {
     const Level &L = P->lev[level];
     const int R = P->R;
+    if (rzp && (sizeof(T) != 8 || P->G != 1 || (mode != kPassPlain && mode != kPassTwice)))
+        return hipErrorInvalidValue;
     const Seg *tab = nullptr;
     int cnt;
     const int64_t rb = L.coff[k], re = L.coff[k + 1];
@@ -672,9 +716,14 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         // skips only the diagonal (every other colour is already written)
         if (mode == kPassTwiceZeroStart && (!L.zs_std || k != L.ncol - 1 || L.ncol != 8)) return hipErrorInvalidValue;
 #define MG_TWICE_LAUNCH(SKIPM, NT, D8)                                                                  \
-    MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, \
-                                                                                tab, rb, re, done, nullptr, \
-                                                                                nullptr)));
+    if (rzp && SKIPM == 0u) {                                                                          \
+        if constexpr (sizeof(T) == 8)                                                                  \
+            MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true, true><<<cnt, pass_block(NT), 0, s>>>(  \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp))); \
+    } else {                                                                                           \
+        MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true><<<cnt, pass_block(NT), 0, s>>>(            \
+                             L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr))); \
+    }
 #define MG_TWICE_MODE(SKIPM)                                                                            \
     if (L.stream_nt) {                                                                                 \
         if (L.dcol) { MG_TWICE_LAUNCH(SKIPM, true, true) } else { MG_TWICE_LAUNCH(SKIPM, true, false) }    \
@@ -705,8 +754,15 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         return hipGetLastError();
     }
 #define MG_PASS_LAUNCH(NT, M, D8)                                                                      \
-    MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, D8><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, r, z, tab, \
-                                                                      rb, re, done, coarse, ic)));
+    if (M == 0 && rzp) {                                                                               \
+        if constexpr (sizeof(T) == 8)                                                                  \
+            MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, 0, D8, false, true><<<cnt, pass_block(NT), 0, s>>>(    \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp)));  \
+    } else {                                                                                           \
+        MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, D8><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, \
+                                                                          r, z, tab, rb, re, done, coarse, ic, \
+                                                                          nullptr)));             \
+    }
 #define MG_PASS_MODE(M)                                                                                \
     if (L.stream_nt) {                                                                                 \
         if (L.dcol) { MG_PASS_LAUNCH(true, M, true) } else { MG_PASS_LAUNCH(true, M, false) }            \
@@ -727,9 +783,9 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     return hipGetLastError();
 }
 template hipError_t launch_pass<double>(const mgpcg_problem *, int, int, int, const double *,
-                                        const double *, double *, const int *, double *, hipStream_t);
+                                        const double *, double *, const int *, double *, hipStream_t, double *);
 template hipError_t launch_pass<float>(const mgpcg_problem *, int, int, int, const float *,
-                                       const float *, float *, const int *, float *, hipStream_t);
+                                       const float *, float *, const int *, float *, hipStream_t, double *);
 
 // --------------------------------------------- persistent coarse V-cycle
 //
@@ -1228,30 +1284,6 @@ hipError_t launch_theta_grad(const double *lam, const double *x, const double *t
 
 enum Kind { kInit = 0, kRz = 1, kPq = 2, kRr = 3 };
 
-// wave-shuffle + LDS tree of per-rhs sums; thread v < R gets the total of rhs v
-template <int R>
-__device__ __forceinline__ double block_sum(double acc, double *sh) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off >= R; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    __syncthreads();
-    if (lane < R) sh[w * R + lane] = acc;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x < R) {
-        t = sh[threadIdx.x];
-#pragma unroll
-        for (int k = 1; k < kBlock / 64; ++k) t += sh[k * R + threadIdx.x];
-    }
-    return t;
-}
-
-template <int R>
-__device__ __forceinline__ void store_partial(double acc, int blk, double *partials) {
-    __shared__ double sh[(kBlock / 64) * R];
-    const double t = block_sum<R>(acc, sh);
-    if (threadIdx.x < R) partials[(int64_t)blk * R + threadIdx.x] = t;
-}
 
 // all R systems of grid g finished?
 template <int R>
@@ -1510,6 +1542,7 @@ hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s) {
     if (e != hipSuccess) return e;
     return finalize<kRz>(P, 1, 0.0, 0, s);
 }
+hipError_t launch_finalize_rz(const mgpcg_problem *P, hipStream_t s) { return finalize<kRz>(P, 2, 0.0, 0, s); }
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s) {
     const bool one = P->G == 1;
     MG_DISPATCH_R(P->R, (k_update_p<RR><<<P->n_red[1], kBlock, 0, s>>>(P->z, P->p, one ? nullptr : P->red_tab[1],

@@ -408,6 +408,21 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             ST_TRY(upload(&P->red_tab[t], tab, s));
             ST_TRY(upload(&P->red_gb[t], gb, s));
         }
+        // <r,z> fused into the level-0 post-smoother: one grid and one
+        // right-hand side (several would multiply the partials the single
+        // finalize workgroup sums), FP64 V-cycle (whose level-0 z is the CG
+        // z), the standard sweep with the double pass (the last update of
+        // colour c-1 is that pass)
+        P->fuse_rz = G == 1 && R == 1 && P->mg_dtype == MGPCG_FP64 && L0.ncol == 8;
+        if (P->fuse_rz) {
+            const int rows = pass_block(L0.stream_nt) / R;
+            P->rz_off[0] = 0;
+            for (int k = 0; k < 8; ++k)
+                P->rz_off[k + 1] = P->rz_off[k] + (L0.coff[k + 1] - L0.coff[k] + rows - 1) / rows;
+            std::vector<int> gb = {0, (int)P->rz_off[8]};
+            ST_TRY(upload(&P->red_gb[2], gb, s));
+            max_blocks = std::max<int64_t>(max_blocks, P->rz_off[8]);
+        }
         const int64_t n0 = L0.n * R;
         ST_TRY(dalloc(&P->x, n0));
         ST_TRY(dalloc(&P->r, n0));
@@ -551,6 +566,7 @@ void free_problem(mgpcg_problem *P) {
     for (auto &p : P->d_natoff) dfree(p);
     dfree(P->d_dims0); dfree(P->d_natoff0);
     for (int t = 0; t < 2; ++t) { dfree(P->red_tab[t]); dfree(P->red_gb[t]); }
+    dfree(P->red_gb[2]);
     dfree(P->x); dfree(P->r); dfree(P->z); dfree(P->p); dfree(P->q); dfree(P->b);
     Scalars &sc = P->sc;
     dfree(sc.rho); dfree(sc.rho_old); dfree(sc.alpha); dfree(sc.beta); dfree(sc.nr0); dfree(sc.pq);
@@ -572,7 +588,7 @@ void free_problem(mgpcg_problem *P) {
 // the first forward pass, last_mode to the last backward pass.
 template <typename T>
 hipError_t sweep(const mgpcg_problem *P, int l, const T *val, const T *r, T *z, int first_mode,
-                 int last_mode, T *coarse, const int *done, hipStream_t s) {
+                 int last_mode, T *coarse, const int *done, hipStream_t s, double *rzp = nullptr) {
     const Level &Lv = P->lev[l];
     const int c = Lv.ncol;
     hipError_t e;
@@ -588,11 +604,14 @@ hipError_t sweep(const mgpcg_problem *P, int l, const T *val, const T *r, T *z, 
         if (k == c - 1 && twice) mode = zs ? kPassTwiceZeroStart : kPassTwice;
         if (zs01 && k == 0) mode = kPassZeroStart01;
         if (zs01 && k == 1) continue;
-        if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s)) != hipSuccess) return e;
+        // rzp: the last update of each colour also writes <r,z> partials
+        double *kp = rzp && k == c - 1 && twice ? rzp + P->rz_off[k] * P->R : nullptr;
+        if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s, kp)) != hipSuccess) return e;
     }
     for (int k = (twice ? c - 2 : c - 1); k >= 0; --k) {
         const int mode = k == 0 ? last_mode : kPassPlain;
-        if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s)) != hipSuccess) return e;
+        double *kp = rzp ? rzp + P->rz_off[k] * P->R : nullptr;
+        if ((e = launch_pass<T>(P, l, k, mode, val, r, z, done, coarse, s, kp)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -608,7 +627,8 @@ const float *level_val<float>(const mgpcg_problem *P, int l) { return P->lev[l].
 // persistent coarse kernel, levels coarse_lc..L-1 run in one launch between
 // the level-0 pre- and post-smoothers.
 template <typename T>
-hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, hipStream_t s) {
+hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, hipStream_t s,
+                  double *rzp = nullptr) {
     const bool persistent = P->coarse_ok && P->coarse_mode == 1;
     const bool tail = !persistent && P->tail_ok;
     // levels below L run one kernel per pass; the rest in one launch
@@ -640,15 +660,16 @@ hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, h
         const bool fuse = P->lev[l].fuse_transfers;
         if (!fuse && (e = launch_prolong<T>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
         if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), fuse ? kPassProlong : kPassPlain, kPassPlain,
-                          zl(l + 1), done, s)) != hipSuccess)
+                          zl(l + 1), done, s, l == 0 ? rzp : nullptr)) != hipSuccess)
             return e;
     }
     return hipSuccess;
 }
 
 // z = M^{-1} r on the CG vectors (FP64, internal layout)
-hipError_t precondition(const mgpcg_problem *P, const double *r, double *z, const int *done, hipStream_t s) {
-    if (P->mg_dtype == MGPCG_FP64) return vcycle<double>(P, r, z, done, s);
+hipError_t precondition(const mgpcg_problem *P, const double *r, double *z, const int *done, hipStream_t s,
+                        double *rzp = nullptr) {
+    if (P->mg_dtype == MGPCG_FP64) return vcycle<double>(P, r, z, done, s, rzp);
     const Level &L0 = P->lev[0];
     hipError_t e;
     const int64_t n = L0.n * P->R;
@@ -659,8 +680,10 @@ hipError_t precondition(const mgpcg_problem *P, const double *r, double *z, cons
 
 hipError_t cg_iteration(mgpcg_problem *P, double tol, hipStream_t s) {
     hipError_t e;
-    if ((e = precondition(P, P->r, P->z, P->sc.done, s)) != hipSuccess) return e;
-    if ((e = launch_dot_rz(P, s)) != hipSuccess) return e;
+    // rho = <r, z>: accumulated by the level-0 post-smoother when fuse_rz
+    if ((e = precondition(P, P->r, P->z, P->sc.done, s, P->fuse_rz ? P->sc.partials : nullptr)) != hipSuccess)
+        return e;
+    if ((e = P->fuse_rz ? launch_finalize_rz(P, s) : launch_dot_rz(P, s)) != hipSuccess) return e;
     if ((e = launch_update_p(P, s)) != hipSuccess) return e;
     if ((e = launch_spmv_pq(P, s)) != hipSuccess) return e;
     return launch_update_xr(P, tol, P->hist_cap, s);

@@ -169,9 +169,14 @@ struct mgpcg_problem {
     // level-0 reduction tables (grid-homogeneous segments, grouped by grid):
     // [0] one row per thread (SpMV-type CG kernels), [1] kVecRows rows per
     // thread (vector kernels).  gb: G+1 first table entry of each grid.
+    // red_gb[2] covers the <r,z> partials that the level-0 post-smoother
+    // writes when fuse_rz is set (one per workgroup of its last update of
+    // each colour; colour k's start at rz_off[k]).
     mg::Seg *red_tab[2] = {nullptr, nullptr};
     int n_red[2] = {0, 0};
-    int *red_gb[2] = {nullptr, nullptr};
+    int *red_gb[3] = {nullptr, nullptr, nullptr};
+    bool fuse_rz = false;
+    int64_t rz_off[9] = {};
 
     // CG vectors, level 0, internal layout, n0*R doubles
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr;
