@@ -39,11 +39,12 @@ hipError_t launch_prolong(const mgpcg_problem *P, int level, const T *zc, T *z, 
 hipError_t launch_coarse_vcycle(const mgpcg_problem *P, bool fp32, hipStream_t s);
 // levels tail_lw..L-1 of one V-cycle in one single-workgroup launch
 hipError_t launch_coarse_tail(const mgpcg_problem *P, bool fp32, hipStream_t s);
-int coarse_vcycle_occupancy(int R, bool fp32, bool d8, int order);  // resident workgroups per CU
+int coarse_vcycle_occupancy(int R, bool fp32, int cf, int order);  // resident workgroups per CU
 
 // delta-code a single-grid level's columns (L.dbase and L.dcol allocated);
-// *bad (device) becomes nonzero if some delta does not fit in int8
-hipError_t launch_delta_encode(const mgpcg_problem *P, int level, const int64_t *coff_dev, int *bad,
+// flags[0] (device) becomes nonzero if some delta does not fit in int8,
+// flags[1] if some real entry has a nonzero delta
+hipError_t launch_delta_encode(const mgpcg_problem *P, int level, const int64_t *coff_dev, int *flags,
                                hipStream_t s);
 
 hipError_t launch_cast_d2f(const double *src, float *dst, int64_t n, hipStream_t s);

@@ -84,10 +84,10 @@ struct Base27 {
 // storage form (packed 8-bit deltas, or 32-bit columns).  Keeping the raw
 // words lets a load be in flight across a barrier: nothing uses them until
 // the columns are decoded.
-template <typename T, bool D8>
+template <typename T, int CF>
 struct RawRow {
     T a[kW];
-    uint32_t w[D8 ? kDeltaWords : kW];
+    uint32_t w[CF ? kDeltaWords : kW];
 };
 
 template <uint32_t SKIP, int q>
@@ -98,10 +98,14 @@ constexpr bool word_needed() {
 
 // The column data are loaded first: the gathers need only them (not the
 // values), so they can leave while the value loads are still streaming.
-template <typename T, uint32_t SKIP, bool NT, bool D8>
+template <typename T, uint32_t SKIP, bool NT, int CF>
 __device__ __forceinline__ void load_raw(const T *__restrict__ val, const int32_t *__restrict__ col,
-                                         const int8_t *__restrict__ dcol, int64_t i, RawRow<T, D8> &rw) {
-    if constexpr (D8) {
+                                         const int8_t *__restrict__ dcol, int64_t i, RawRow<T, CF> &rw) {
+    if constexpr (CF == 2) {
+        // every delta is zero: the columns are implied by the bases
+#pragma unroll
+        for (int q = 0; q < kDeltaWords; ++q) rw.w[q] = 0u;
+    } else if constexpr (CF == 1) {
         const uint32_t *dw = (const uint32_t *)dcol;
 #define MG_LOAD_WORD(q) rw.w[q] = word_needed<SKIP, q>() ? ld<NT>(dw + delta_word(q, i)) : 0u;
         MG_LOAD_WORD(0) MG_LOAD_WORD(1) MG_LOAD_WORD(2) MG_LOAD_WORD(3)
@@ -122,9 +126,9 @@ __device__ __forceinline__ void load_raw(const T *__restrict__ val, const int32_
 }
 
 // absolute column of slot s of row i
-template <bool D8, typename T, class SB>
-__device__ __forceinline__ int32_t slot_col(const RawRow<T, D8> &rw, const SB &sb, int64_t i, int s) {
-    if constexpr (D8) {
+template <int CF, typename T, class SB>
+__device__ __forceinline__ int32_t slot_col(const RawRow<T, CF> &rw, const SB &sb, int64_t i, int s) {
+    if constexpr (CF) {
         const int32_t dl = (int32_t)(rw.w[s / 4] << (24 - 8 * (s % 4))) >> 24;  // sign-extended byte
         return (int32_t)(i + sb[s] + dl);
     } else {
@@ -137,13 +141,13 @@ __device__ __forceinline__ int32_t slot_col(const RawRow<T, D8> &rw, const SB &s
 // [0, n), so delta-coded columns are clamped.  Real columns are unchanged
 // by the clamp; a padding slot's gather then reads some valid row and its
 // value is never used (the sums skip slots whose value is 0).
-template <uint32_t SKIP, bool D8, typename T, class SB>
-__device__ __forceinline__ void decode_cols(const RawRow<T, D8> &rw, const SB &sb, int64_t n, int64_t i,
+template <uint32_t SKIP, int CF, typename T, class SB>
+__device__ __forceinline__ void decode_cols(const RawRow<T, CF> &rw, const SB &sb, int64_t n, int64_t i,
                                             int32_t (&c)[kW]) {
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
-        int32_t cs = ((SKIP >> s) & 1u) ? 0 : slot_col<D8>(rw, sb, i, s);
-        if constexpr (D8) cs = min(max(cs, 0), (int32_t)(n - 1));
+        int32_t cs = ((SKIP >> s) & 1u) ? 0 : slot_col<CF>(rw, sb, i, s);
+        if constexpr (CF) cs = min(max(cs, 0), (int32_t)(n - 1));
         c[s] = cs;
     }
 }
@@ -152,15 +156,15 @@ __device__ __forceinline__ void decode_cols(const RawRow<T, D8> &rw, const SB &s
 // All value and column loads of the row are issued before anything uses
 // them, so a wave keeps 34 streaming loads (27 with 32-bit columns: 54) in
 // flight, and then its 27 gathers.
-template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
+template <typename T, int R, uint32_t SKIP, bool NT, int CF, class SB>
 __device__ __forceinline__ void load_slots(const T *__restrict__ val, const int32_t *__restrict__ col,
                                            const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
                                            T (&a)[kW], int32_t (&c)[kW]) {
-    RawRow<T, D8> rw;
-    load_raw<T, SKIP, NT, D8>(val, col, dcol, i, rw);
+    RawRow<T, CF> rw;
+    load_raw<T, SKIP, NT, CF>(val, col, dcol, i, rw);
 #pragma unroll
     for (int s = 0; s < kW; ++s) a[s] = rw.a[s];
-    decode_cols<SKIP, D8>(rw, sb, n, i, c);
+    decode_cols<SKIP, CF>(rw, sb, n, i, c);
 }
 
 // x at the 27 columns (0 for skipped slots).  The gathers depend on the
@@ -182,12 +186,12 @@ __device__ __forceinline__ void gather_slots(const T *x, int v, const T (&a)[kW]
 // the value loads are still streaming.  (Predicting the columns and gathering
 // together with the operator loads, with a check afterwards, was measured
 // slower on the latency-bound levels: ~4.45 against ~4.0 us per level-2 pass.)
-template <typename T, int R, uint32_t SKIP, bool NT, bool D8, class SB>
+template <typename T, int R, uint32_t SKIP, bool NT, int CF, class SB>
 __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
                                          const T *x, int v, T (&a)[kW], T (&xv)[kW]) {
     int32_t c[kW];
-    load_slots<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, a, c);
+    load_slots<T, R, SKIP, NT, CF>(val, col, dcol, sb, n, i, a, c);
     gather_slots<T, R, SKIP>(x, v, a, c, xv);
 }
 
@@ -197,12 +201,12 @@ __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_
 // 54 streaming loads and then 27 gathers in flight.  Slots whose bit is set
 // in the compile-time SKIP mask are left out entirely (their x is known to be
 // zero); the diagonal value is always loaded and returned in d.
-template <typename T, int R, uint32_t SKIP, bool NT, bool D8>
+template <typename T, int R, uint32_t SKIP, bool NT, int CF>
 __device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *__restrict__ col,
                                      const int8_t *__restrict__ dcol, const int32_t *__restrict__ sb, int64_t n,
                                      int64_t i, const T *x, int v, T &d) {
     T a[kW], xv[kW];
-    load_row<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, x, v, a, xv);
+    load_row<T, R, SKIP, NT, CF>(val, col, dcol, sb, n, i, x, v, a, xv);
     d = a[kCentre];
     T acc = 0;
 #pragma unroll
@@ -287,35 +291,45 @@ hipError_t launch_build_ell(const mgpcg_problem *P, int level, const double *the
 }
 
 // Delta-code the columns of one (single-grid) level: dcol = col - i - base,
-// for real entries only; `bad` is set when some delta does not fit in int8.
+// for real entries only.  flags[0]: some delta does not fit in int8;
+// flags[1]: some real entry has a nonzero delta (both reduced per wave
+// before one atomic each).
 __global__ __launch_bounds__(kBlock) void k_delta_encode(int64_t n, const double *__restrict__ val64,
                                                          const float *__restrict__ val32,
                                                          const int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ base,
                                                          const int64_t *__restrict__ coff, int ncol,
-                                                         int8_t *__restrict__ dcol, int *__restrict__ bad) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int k = colour_of(coff, ncol, i);
+                                                         int8_t *__restrict__ dcol, int *__restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool bad = false, nonzero = false;
+    if (i < n) {
+        const int k = colour_of(coff, ncol, i);
 #pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const int64_t e = ell_index(s, i);
-        const bool real = val64 ? val64[e] != 0.0 : val32[e] != 0.0f;
-        int64_t dlt = real ? (int64_t)col[e] - i - base[k * kW + s] : 0;
-        if (dlt < -128 || dlt > 127) {
-            atomicOr(bad, 1);
-            dlt = 0;
+        for (int s = 0; s < kW; ++s) {
+            const int64_t e = ell_index(s, i);
+            const bool real = val64 ? val64[e] != 0.0 : val32[e] != 0.0f;
+            int64_t dlt = real ? (int64_t)col[e] - i - base[k * kW + s] : 0;
+            nonzero = nonzero || dlt != 0;
+            if (dlt < -128 || dlt > 127) {
+                bad = true;
+                dlt = 0;
+            }
+            dcol[4 * delta_word(s / 4, i) + s % 4] = (int8_t)dlt;
         }
-        dcol[4 * delta_word(s / 4, i) + s % 4] = (int8_t)dlt;
+    }
+    const bool any_bad = __any(bad), any_nonzero = __any(nonzero);
+    if ((threadIdx.x & 63) == 0) {
+        if (any_bad) atomicOr(&flags[0], 1);
+        if (any_nonzero) atomicOr(&flags[1], 1);
     }
 }
 
-hipError_t launch_delta_encode(const mgpcg_problem *P, int level, const int64_t *coff_dev, int *bad,
+hipError_t launch_delta_encode(const mgpcg_problem *P, int level, const int64_t *coff_dev, int *flags,
                                hipStream_t s) {
     const Level &L = P->lev[level];
     if (L.n == 0) return hipSuccess;
     k_delta_encode<<<nblocks(L.n), kBlock, 0, s>>>(L.n, L.val64, L.val32, L.col, L.dbase, coff_dev, L.ncol,
-                                                   L.dcol, bad);
+                                                   L.dcol, flags);
     return hipGetLastError();
 }
 
@@ -366,7 +380,7 @@ hipError_t launch_permute(const mgpcg_problem *P, int level, const double *src, 
 
 // y = A x over all rows; one thread per (row, rhs).  The R lanes of a row
 // load the same operator entry (one transaction) and R consecutive x values.
-template <typename T, int R, bool D8>
+template <typename T, int R, int CF>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
                                                  const int32_t *__restrict__ dbase, CoffTable ct,
@@ -375,9 +389,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const T *__restrict_
     if (gid >= n * R) return;
     int64_t i = gid / R;
     int v = (int)(gid % R);
-    const int32_t *sb = D8 ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
+    const int32_t *sb = CF ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
     T d;
-    y[gid] = row_sum<T, R, 0u, true, D8>(val, col, dcol, sb, n, i, x, v, d);
+    y[gid] = row_sum<T, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
 }
 
 template <typename T>
@@ -386,13 +400,11 @@ hipError_t launch_spmv(const mgpcg_problem *P, int level, const T *val, const T 
     int64_t work = L.n * P->R;
     if (work == 0) return hipSuccess;
     const CoffTable ct = coff_table(L);
-    if (L.dcol) {
-        MG_DISPATCH_R(P->R, (k_spmv<T, RR, true><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol, L.dbase,
-                                                                               ct, x, y)));
-    } else {
-        MG_DISPATCH_R(P->R, (k_spmv<T, RR, false><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol,
-                                                                                L.dbase, ct, x, y)));
-    }
+#define MG_SPMV(CFV)                                                                                   \
+    MG_DISPATCH_R(P->R, (k_spmv<T, RR, CFV><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol, L.dbase, ct, \
+                                                                            x, y)));
+    if (L.cf == 2) { MG_SPMV(2) } else if (L.cf == 1) { MG_SPMV(1) } else { MG_SPMV(0) }
+#undef MG_SPMV
     return hipGetLastError();
 }
 template hipError_t launch_spmv<double>(const mgpcg_problem *, int, const double *, const double *,
@@ -491,7 +503,7 @@ __device__ __forceinline__ void store_partial(double acc, int blk, double *parti
 // is the system's convergence flag: it is loaded with the operator and only
 // the stores wait for it, so a pass does not begin with a round trip.
 // Returns r_i times the stored z_i when DOT (for <r, z>), else 0.
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, class SB, bool TWICE = false,
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, class SB, bool TWICE = false,
           bool DOT = false>
 __device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb,
@@ -506,7 +518,7 @@ __device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val,
     int64_t co = 0;
     if (MODE != 0) co = (int64_t)inj_coarse[i - inj_base] * R + v;
     T a[kW], xv[kW];
-    load_row<T, R, SKIP, NT, D8>(val, col, dcol, sb, n, i, z, v, a, xv);
+    load_row<T, R, SKIP, NT, CF>(val, col, dcol, sb, n, i, z, v, a, xv);
     T zc = T(0);
     if (MODE == 2) zc = coarse[co];
     // z_i before this pass (refined in MODE 2); 0 on a zero start
@@ -530,7 +542,7 @@ __device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val,
 
 // DOT (one grid, no table): each workgroup also writes the sum of r_i z_i
 // over its rows to rzp[b * R + rhs].
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE, bool D8, bool TWICE = false, bool DOT = false>
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, bool TWICE = false, bool DOT = false>
 __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
                                                  const Base27 sb,
@@ -557,7 +569,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
         // every thread takes part in the workgroup's sum
         double rz = 0.0;
         if (rl < count)
-            rz = pass_row<T, R, SKIP, NT, MODE, D8, Base27, TWICE, true>(
+            rz = pass_row<T, R, SKIP, NT, MODE, CF, Base27, TWICE, true>(
                 n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse, inj_coarse, done ? done + v : nullptr);
         store_partial<R, pass_block(NT)>(rz, b, rzp);
     } else {
@@ -565,7 +577,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
         // several grids: a converged grid is skipped before anything is
         // loaded; one grid: its flag travels with the loads
         if (tab && done && done[grid * R + v]) return;
-        pass_row<T, R, SKIP, NT, MODE, D8, Base27, TWICE>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base,
+        pass_row<T, R, SKIP, NT, MODE, CF, Base27, TWICE>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base,
                                                          coarse, inj_coarse, tab || !done ? nullptr : done + v);
     }
 }
@@ -575,7 +587,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
 // colour-0 neighbours, whose values this kernel forms on the fly with the
 // same expression instead of waiting for them.  Rows [coff0, coff2) hold both
 // colours contiguously (colour-major layout).
-template <typename T, int R, bool NT, bool D8, int ORD>
+template <typename T, int R, bool NT, int CF, int ORD>
 __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T *__restrict__ val,
                                                       const int32_t *__restrict__ col,
                                                       const int8_t *__restrict__ dcol, const Base27 sb1,
@@ -611,7 +623,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
     constexpr uint32_t SKIP = zs_mask(1, ORD);
     T a[kW];
     int32_t c[kW];
-    load_slots<T, R, SKIP, NT, D8>(val, col, dcol, sb1, n, i, a, c);
+    load_slots<T, R, SKIP, NT, CF>(val, col, dcol, sb1, n, i, a, c);
     T rj[kW], dj[kW];
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
@@ -635,13 +647,13 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
     if (!dv) z[o] = (rv - acc + zi * d) / d;
 }
 
-template <typename T, int R, bool NT, bool D8>
+template <typename T, int R, bool NT, int CF>
 static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T *val, const int32_t *col,
                     const int8_t *dcol, const Base27 &sb, const T *r, T *z, const Seg *tab, int64_t rb,
                     int64_t re, const int *done) {
 #define MG_ZS_CASE(K, O)                                                                              \
     case K + 8 * O:                                                                                   \
-        k_pass<T, R, zs_mask(K, O), NT, 0, D8><<<cnt, pass_block(NT), 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
+        k_pass<T, R, zs_mask(K, O), NT, 0, CF><<<cnt, pass_block(NT), 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
                                                                       done, nullptr, nullptr, nullptr); \
         break;
     switch (k + 8 * order) {
@@ -679,7 +691,7 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (cnt == 0) return hipSuccess;
     const int32_t *ic = L.inj_coarse;
     Base27 sb;
-    for (int t = 0; t < kW; ++t) sb.v[t] = L.dcol ? L.dbase_host[k * kW + t] : 0;
+    for (int t = 0; t < kW; ++t) sb.v[t] = L.cf ? L.dbase_host[k * kW + t] : 0;
     if (mode == kPassZeroStart01) {
         if (k != 0 || !L.zs_std || L.ncol != 8 || (R != 1 && R != 16)) return hipErrorInvalidValue;
         int cnt01;
@@ -692,20 +704,20 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
             cnt01 = (int)((L.coff[2] - L.coff[0] + rows - 1) / rows);
         }
         Base27 sb1;
-        for (int t = 0; t < kW; ++t) sb1.v[t] = L.dcol ? L.dbase_host[1 * kW + t] : 0;
-#define MG_ZS01(RR, NT, D8)                                                                             \
+        for (int t = 0; t < kW; ++t) sb1.v[t] = L.cf ? L.dbase_host[1 * kW + t] : 0;
+#define MG_ZS01(RR, NT, CF)                                                                             \
     if (P->colour_order)                                                                               \
-        k_pass_zs01<T, RR, NT, D8, 1><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
+        k_pass_zs01<T, RR, NT, CF, 1><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
                                                             L.coff[0], L.coff[1], L.coff[2], done);      \
     else                                                                                               \
-        k_pass_zs01<T, RR, NT, D8, 0><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
+        k_pass_zs01<T, RR, NT, CF, 0><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
                                                             L.coff[0], L.coff[1], L.coff[2], done);
-#define MG_ZS01_R(NT, D8)                                                                               \
-    if (R == 1) { MG_ZS01(1, NT, D8) } else { MG_ZS01(16, NT, D8) }
+#define MG_ZS01_R(NT, CF)                                                                               \
+    if (R == 1) { MG_ZS01(1, NT, CF) } else { MG_ZS01(16, NT, CF) }
         if (L.stream_nt) {
-            if (L.dcol) { MG_ZS01_R(true, true) } else { MG_ZS01_R(true, false) }
+            if (L.cf == 2) { MG_ZS01_R(true, 2) } else if (L.cf == 1) { MG_ZS01_R(true, 1) } else { MG_ZS01_R(true, 0) }
         } else {
-            if (L.dcol) { MG_ZS01_R(false, true) } else { MG_ZS01_R(false, false) }
+            if (L.cf == 2) { MG_ZS01_R(false, 2) } else if (L.cf == 1) { MG_ZS01_R(false, 1) } else { MG_ZS01_R(false, 0) }
         }
 #undef MG_ZS01_R
 #undef MG_ZS01
@@ -715,20 +727,20 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         // colour k swept twice in a row; on a zero start its first update
         // skips only the diagonal (every other colour is already written)
         if (mode == kPassTwiceZeroStart && (!L.zs_std || k != L.ncol - 1 || L.ncol != 8)) return hipErrorInvalidValue;
-#define MG_TWICE_LAUNCH(SKIPM, NT, D8)                                                                  \
+#define MG_TWICE_LAUNCH(SKIPM, NT, CF)                                                                  \
     if (rzp && SKIPM == 0u) {                                                                          \
         if constexpr (sizeof(T) == 8)                                                                  \
-            MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true, true><<<cnt, pass_block(NT), 0, s>>>(  \
+            MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true, true><<<cnt, pass_block(NT), 0, s>>>(  \
                                  L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp))); \
     } else {                                                                                           \
-        MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, D8, true><<<cnt, pass_block(NT), 0, s>>>(            \
+        MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true><<<cnt, pass_block(NT), 0, s>>>(            \
                              L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr))); \
     }
 #define MG_TWICE_MODE(SKIPM)                                                                            \
     if (L.stream_nt) {                                                                                 \
-        if (L.dcol) { MG_TWICE_LAUNCH(SKIPM, true, true) } else { MG_TWICE_LAUNCH(SKIPM, true, false) }    \
+        if (L.cf == 2) { MG_TWICE_LAUNCH(SKIPM, true, 2) } else if (L.cf == 1) { MG_TWICE_LAUNCH(SKIPM, true, 1) } else { MG_TWICE_LAUNCH(SKIPM, true, 0) }    \
     } else {                                                                                           \
-        if (L.dcol) { MG_TWICE_LAUNCH(SKIPM, false, true) } else { MG_TWICE_LAUNCH(SKIPM, false, false) }  \
+        if (L.cf == 2) { MG_TWICE_LAUNCH(SKIPM, false, 2) } else if (L.cf == 1) { MG_TWICE_LAUNCH(SKIPM, false, 1) } else { MG_TWICE_LAUNCH(SKIPM, false, 0) }  \
     }
         if (mode == kPassTwiceZeroStart) {
             MG_TWICE_MODE(zs_mask(7, 0))
@@ -742,32 +754,32 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (mode == kPassZeroStart) {
         if (!L.zs_std || (R != 1 && R != 16)) return hipErrorInvalidValue;
         const int ord = P->colour_order;
-#define MG_ZS_LAUNCH(NT, D8)                                                                           \
-    if (R == 1) pass_zs<T, 1, NT, D8>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done); \
-    else pass_zs<T, 16, NT, D8>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done);
+#define MG_ZS_LAUNCH(NT, CF)                                                                           \
+    if (R == 1) pass_zs<T, 1, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done); \
+    else pass_zs<T, 16, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done);
         if (L.stream_nt) {
-            if (L.dcol) { MG_ZS_LAUNCH(true, true) } else { MG_ZS_LAUNCH(true, false) }
+            if (L.cf == 2) { MG_ZS_LAUNCH(true, 2) } else if (L.cf == 1) { MG_ZS_LAUNCH(true, 1) } else { MG_ZS_LAUNCH(true, 0) }
         } else {
-            if (L.dcol) { MG_ZS_LAUNCH(false, true) } else { MG_ZS_LAUNCH(false, false) }
+            if (L.cf == 2) { MG_ZS_LAUNCH(false, 2) } else if (L.cf == 1) { MG_ZS_LAUNCH(false, 1) } else { MG_ZS_LAUNCH(false, 0) }
         }
 #undef MG_ZS_LAUNCH
         return hipGetLastError();
     }
-#define MG_PASS_LAUNCH(NT, M, D8)                                                                      \
+#define MG_PASS_LAUNCH(NT, M, CF)                                                                      \
     if (M == 0 && rzp) {                                                                               \
         if constexpr (sizeof(T) == 8)                                                                  \
-            MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, 0, D8, false, true><<<cnt, pass_block(NT), 0, s>>>(    \
+            MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, 0, CF, false, true><<<cnt, pass_block(NT), 0, s>>>(    \
                                  L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp)));  \
     } else {                                                                                           \
-        MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, D8><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, \
+        MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, CF><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, \
                                                                           r, z, tab, rb, re, done, coarse, ic, \
                                                                           nullptr)));             \
     }
 #define MG_PASS_MODE(M)                                                                                \
     if (L.stream_nt) {                                                                                 \
-        if (L.dcol) { MG_PASS_LAUNCH(true, M, true) } else { MG_PASS_LAUNCH(true, M, false) }            \
+        if (L.cf == 2) { MG_PASS_LAUNCH(true, M, 2) } else if (L.cf == 1) { MG_PASS_LAUNCH(true, M, 1) } else { MG_PASS_LAUNCH(true, M, 0) }            \
     } else {                                                                                           \
-        if (L.dcol) { MG_PASS_LAUNCH(false, M, true) } else { MG_PASS_LAUNCH(false, M, false) }          \
+        if (L.cf == 2) { MG_PASS_LAUNCH(false, M, 2) } else if (L.cf == 1) { MG_PASS_LAUNCH(false, M, 1) } else { MG_PASS_LAUNCH(false, M, 0) }          \
     }
     if (mode == kPassRestrict) {
         if (!L.fuse_transfers) return hipErrorInvalidValue;
@@ -843,23 +855,23 @@ __device__ __forceinline__ bool grid_barrier(unsigned *flags, int B, unsigned ep
     return s_ok != 0;
 }
 
-template <typename T, int R, bool D8, uint32_t SKIP, int MODE, bool TWICE = false>
+template <typename T, int R, int CF, uint32_t SKIP, int MODE, bool TWICE = false>
 __device__ __forceinline__ void coarse_phase(const CoarseLevel &lv, int k, T *coarse, int bid, int B) {
-    const int32_t *sb = D8 ? lv.dbase + k * kW : nullptr;
+    const int32_t *sb = CF ? lv.dbase + k * kW : nullptr;
     const int64_t r0 = lv.coff[k], r1 = lv.coff[k + 1];
     const int rpb = blockDim.x / R;
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
     for (int64_t base = r0 + (int64_t)bid * rpb; base < r1; base += (int64_t)B * rpb) {
         const int64_t i = base + rl;
         if (i < r1)
-            pass_row<T, R, SKIP, false, MODE, D8, const int32_t *, TWICE>(
+            pass_row<T, R, SKIP, false, MODE, CF, const int32_t *, TWICE>(
                 lv.n, (const T *)lv.val, lv.col, lv.dcol, sb, (const T *)lv.r, (T *)lv.z, i, v, r0, coarse,
                 lv.inj_coarse);
     }
 }
 
 // separate restriction / refinement phases (when they cannot ride on a pass)
-template <typename T, int R, bool D8>
+template <typename T, int R, int CF>
 __device__ __forceinline__ void coarse_restrict(const CoarseLevel &lv, T *rc, int bid, int B) {
     const int rpb = blockDim.x / R;
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
@@ -867,9 +879,9 @@ __device__ __forceinline__ void coarse_restrict(const CoarseLevel &lv, T *rc, in
         const int64_t t = base + rl;
         if (t < lv.n_inj) {
             const int64_t i = lv.inj_fine[t];
-            const int32_t *sb = D8 ? lv.dbase + colour_of(lv.coff, 8, i) * kW : nullptr;
+            const int32_t *sb = CF ? lv.dbase + colour_of(lv.coff, 8, i) * kW : nullptr;
             T d;
-            const T acc = row_sum<T, R, 0u, false, D8>((const T *)lv.val, lv.col, lv.dcol, sb, lv.n, i,
+            const T acc = row_sum<T, R, 0u, false, CF>((const T *)lv.val, lv.col, lv.dcol, sb, lv.n, i,
                                                       (const T *)lv.z, v, d);
             rc[(int64_t)lv.inj_coarse[t] * R + v] = ((const T *)lv.r)[i * R + v] - acc;
         }
@@ -890,18 +902,18 @@ __device__ __forceinline__ void coarse_prolong(const CoarseLevel &lv, const T *z
     }
 }
 
-template <typename T, int R, bool D8, int ORD>
+template <typename T, int R, int CF, int ORD>
 __device__ __forceinline__ void coarse_run_phase(const CoarseArgs &A, int ph, int bid, int B) {
     const int l = ph & 15, k = (ph >> 4) & 15, op = ph >> 8;
     const CoarseLevel &lv = A.lev[l];
     switch (op) {
         case kOpPlain:
-            coarse_phase<T, R, D8, 0u, 0>(lv, k, nullptr, bid, B);
+            coarse_phase<T, R, CF, 0u, 0>(lv, k, nullptr, bid, B);
             break;
         case kOpZeroStart:
             switch (k) {
 #define MG_ZS_PHASE(K) \
-    case K: coarse_phase<T, R, D8, zs_mask(K, ORD), 0>(lv, K, nullptr, bid, B); break;
+    case K: coarse_phase<T, R, CF, zs_mask(K, ORD), 0>(lv, K, nullptr, bid, B); break;
                 MG_ZS_PHASE(0) MG_ZS_PHASE(1) MG_ZS_PHASE(2) MG_ZS_PHASE(3)
                 MG_ZS_PHASE(4) MG_ZS_PHASE(5) MG_ZS_PHASE(6) MG_ZS_PHASE(7)
 #undef MG_ZS_PHASE
@@ -909,22 +921,22 @@ __device__ __forceinline__ void coarse_run_phase(const CoarseArgs &A, int ph, in
             }
             break;
         case kOpFusedRestrict:
-            coarse_phase<T, R, D8, 0u, 1>(lv, k, (T *)A.lev[l + 1].r, bid, B);
+            coarse_phase<T, R, CF, 0u, 1>(lv, k, (T *)A.lev[l + 1].r, bid, B);
             break;
         case kOpFusedProlong:
-            coarse_phase<T, R, D8, 0u, 2>(lv, k, (T *)A.lev[l + 1].z, bid, B);
+            coarse_phase<T, R, CF, 0u, 2>(lv, k, (T *)A.lev[l + 1].z, bid, B);
             break;
         case kOpRestrict:
-            coarse_restrict<T, R, D8>(lv, (T *)A.lev[l + 1].r, bid, B);
+            coarse_restrict<T, R, CF>(lv, (T *)A.lev[l + 1].r, bid, B);
             break;
         case kOpProlong:
             coarse_prolong<T, R>(lv, (const T *)A.lev[l + 1].z, bid, B);
             break;
         case kOpTwice:
-            coarse_phase<T, R, D8, 0u, 0, true>(lv, k, nullptr, bid, B);
+            coarse_phase<T, R, CF, 0u, 0, true>(lv, k, nullptr, bid, B);
             break;
         case kOpTwiceZeroStart:
-            coarse_phase<T, R, D8, zs_mask(7, ORD), 0, true>(lv, k, nullptr, bid, B);
+            coarse_phase<T, R, CF, zs_mask(7, ORD), 0, true>(lv, k, nullptr, bid, B);
             break;
         default:
             break;
@@ -933,7 +945,7 @@ __device__ __forceinline__ void coarse_run_phase(const CoarseArgs &A, int ph, in
 
 // Executes the host-built phase program (level, colour, operation) with one
 // grid barrier between consecutive phases.
-template <typename T, int R, bool D8, int ORD>
+template <typename T, int R, int CF, int ORD>
 __global__ __launch_bounds__(kBlock) void k_coarse_vcycle(CoarseArgs A) {
     __shared__ unsigned s_base;
     const int B = gridDim.x;
@@ -943,7 +955,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_vcycle(CoarseArgs A) {
     unsigned epoch = s_base;
     bool ok = true;
     for (int p = 0; p < A.nphases; ++p) {
-        if (ok) coarse_run_phase<T, R, D8, ORD>(A, A.phase[p], bid, B);
+        if (ok) coarse_run_phase<T, R, CF, ORD>(A, A.phase[p], bid, B);
         if (p + 1 == A.nphases) break;
         ++epoch;
         if (ok) ok = grid_barrier(A.flags, B, epoch, A.err, A.spin_limit);
@@ -970,10 +982,10 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <typename T, bool D8, uint32_t SKIP>
+template <typename T, int CF, uint32_t SKIP>
 __device__ __forceinline__ void tail_load(const T *val, const int32_t *col, const int8_t *dcol, const CoffTable &ct,
                                           int k,
-                                          RawRow<T, D8> &rw) {
+                                          RawRow<T, CF> &rw) {
     // unconditional (threads past the colour's end load its last row, or
     // row 0), so that the loads are straight-line code the wait counters
     // track exactly
@@ -982,7 +994,7 @@ __device__ __forceinline__ void tail_load(const T *val, const int32_t *col, cons
     // an opaque copy of the row index per pass: the compiler can then not
     // merge these loads with the other sweep's loads of the same colour
     asm volatile("" : "+v"(i));
-    load_raw<T, SKIP, false, D8>(val, col, dcol, i, rw);
+    load_raw<T, SKIP, false, CF>(val, col, dcol, i, rw);
     // keep the loads here: without this the compiler sinks them to their
     // use in the next pass, which would put them back on the critical path
     asm volatile("" ::: "memory");
@@ -997,10 +1009,10 @@ typedef const __attribute__((address_space(4))) int32_t *ConstBases;
 // call load() at the start of each group), the columns decoded from the raw
 // row as they are needed; optionally with the diagonal slot replaced by a
 // given value.
-template <typename T, bool D8, uint32_t SKIP, bool CENTRE>
+template <typename T, int CF, uint32_t SKIP, bool CENTRE>
 struct LdsGather {
     const T *zs;
-    const RawRow<T, D8> &rw;
+    const RawRow<T, CF> &rw;
     ConstBases cb;
     int64_t i;
     T centre;
@@ -1011,7 +1023,7 @@ struct LdsGather {
 #pragma unroll
         for (int s = s0; s < s0 + 9 && s < kW; ++s) {
             const bool use = !((SKIP >> s) & 1u) && rw.a[s] != T(0);
-            const T v = zs[use ? slot_col<D8>(rw, cb, i, s) : 0];
+            const T v = zs[use ? slot_col<CF>(rw, cb, i, s) : 0];
             buf[s] = (CENTRE && s == kCentre) ? centre : (use ? v : T(0));
         }
     }
@@ -1020,28 +1032,28 @@ struct LdsGather {
 
 // one row of a pass with z in LDS (rows of one colour never neighbour each
 // other, so nothing a row reads changes during the pass)
-template <typename T, bool D8, uint32_t SKIP, bool TWICE>
-__device__ __forceinline__ void tail_row(const RawRow<T, D8> &rw, ConstBases cb, const T *rs, T *zs, int64_t i) {
+template <typename T, int CF, uint32_t SKIP, bool TWICE>
+__device__ __forceinline__ void tail_row(const RawRow<T, CF> &rw, ConstBases cb, const T *rs, T *zs, int64_t i) {
     const T rv = rs[i];
-    const T zi = SKIP ? T(0) : zs[slot_col<D8>(rw, cb, i, kCentre)];
-    const T znew = gs_update<T, SKIP, 9>(rw.a, LdsGather<T, D8, SKIP, false>{zs, rw, cb, i, T(0)}, rv, zi);
+    const T zi = SKIP ? T(0) : zs[slot_col<CF>(rw, cb, i, kCentre)];
+    const T znew = gs_update<T, SKIP, 9>(rw.a, LdsGather<T, CF, SKIP, false>{zs, rw, cb, i, T(0)}, rv, zi);
     // a second pass of the same colour: the full row with the new diagonal value
-    zs[i] = TWICE ? gs_update<T, 0u, 9>(rw.a, LdsGather<T, D8, 0u, true>{zs, rw, cb, i, znew}, rv, znew) : znew;
+    zs[i] = TWICE ? gs_update<T, 0u, 9>(rw.a, LdsGather<T, CF, 0u, true>{zs, rw, cb, i, znew}, rv, znew) : znew;
 }
 
 // the rows of colour k (one per thread: the level qualifies only if every
 // colour fits in the workgroup), operators from the prefetched raw rows
-template <typename T, bool D8, uint32_t SKIP, bool TWICE>
-__device__ __forceinline__ void tail_pass(ConstBases cb, const CoffTable &ct, int k, const RawRow<T, D8> &rw,
+template <typename T, int CF, uint32_t SKIP, bool TWICE>
+__device__ __forceinline__ void tail_pass(ConstBases cb, const CoffTable &ct, int k, const RawRow<T, CF> &rw,
                                           const T *rs, T *zs) {
     const int64_t i = ct.coff[k] + threadIdx.x;
-    if (i < ct.coff[k + 1]) tail_row<T, D8, SKIP, TWICE>(rw, cb + k * kW, rs, zs, i);
+    if (i < ct.coff[k + 1]) tail_row<T, CF, SKIP, TWICE>(rw, cb + k * kW, rs, zs, i);
 }
 
 // (the operator pointers are deliberately not __restrict__: that lets the
 // compiler keep the forward sweep's loads of a colour for its backward pass,
 // which does not fit in registers next to the prefetch buffers)
-template <typename T, bool D8, int ORD>
+template <typename T, int CF, int ORD>
 __global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *val, const int32_t *col,
                                                             const int8_t *dcol,
                                                             const int32_t *__restrict__ dbase, CoffTable ct,
@@ -1050,16 +1062,16 @@ __global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *
     const ConstBases tb = (ConstBases)dbase;
     T *rs = (T *)tail_lds;
     T *zs = rs + n;
-    RawRow<T, D8> b0, b1;
-    tail_load<T, D8, zs_mask(0, ORD)>(val, col, dcol, ct, 0, b0);
+    RawRow<T, CF> b0, b1;
+    tail_load<T, CF, zs_mask(0, ORD)>(val, col, dcol, ct, 0, b0);
     for (int64_t i = threadIdx.x; i < n; i += kTailBlock) rs[i] = r[i];
     __syncthreads();
     // forward, zero start (colour k reads only colours < k); colour 7 is the
     // last forward and the first backward pass in one; then backward 6..0.
     // Pass p computes from buffer p % 2 while buffer (p+1) % 2 is refilled.
 #define MG_TAIL_STEP(K, SK, TW, BC, KN, SKN, BN)                                                        \
-    tail_load<T, D8, SKN>(val, col, dcol, ct, KN, BN);                                                 \
-    tail_pass<T, D8, SK, TW>(tb, ct, K, BC, rs, zs);                                                   \
+    tail_load<T, CF, SKN>(val, col, dcol, ct, KN, BN);                                                 \
+    tail_pass<T, CF, SK, TW>(tb, ct, K, BC, rs, zs);                                                   \
     lds_barrier();
     MG_TAIL_STEP(0, zs_mask(0, ORD), false, b0, 1, zs_mask(1, ORD), b1)
     MG_TAIL_STEP(1, zs_mask(1, ORD), false, b1, 2, zs_mask(2, ORD), b0)
@@ -1076,7 +1088,7 @@ __global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *
     MG_TAIL_STEP(2, 0u, false, b0, 1, 0u, b1)
     MG_TAIL_STEP(1, 0u, false, b1, 0, 0u, b0)
 #undef MG_TAIL_STEP
-    tail_pass<T, D8, 0u, false>(tb, ct, 0, b0, rs, zs);
+    tail_pass<T, CF, 0u, false>(tb, ct, 0, b0, rs, zs);
     __syncthreads();
     for (int64_t i = threadIdx.x; i < n; i += kTailBlock) z[i] = zs[i];
 }
@@ -1087,17 +1099,17 @@ hipError_t launch_coarse_tail(const mgpcg_problem *P, bool fp32, hipStream_t s) 
     if (P->R != 1 || L.ncol != 8) return hipErrorInvalidValue;
     const CoffTable ct = coff_table(L);
     const size_t lds = (size_t)L.n * 2 * (fp32 ? sizeof(float) : sizeof(double));
-#define MG_TAIL(T, VAL, D8)                                                                            \
+#define MG_TAIL(T, VAL, CF)                                                                            \
     if (P->colour_order)                                                                               \
-        k_coarse_tail<T, D8, 1><<<1, kTailBlock, lds, s>>>(L.n, VAL, L.col, L.dcol, L.dbase, ct, (const T *)L.r, \
+        k_coarse_tail<T, CF, 1><<<1, kTailBlock, lds, s>>>(L.n, VAL, L.col, L.dcol, L.dbase, ct, (const T *)L.r, \
                                                           (T *)L.z);                                    \
     else                                                                                               \
-        k_coarse_tail<T, D8, 0><<<1, kTailBlock, lds, s>>>(L.n, VAL, L.col, L.dcol, L.dbase, ct, (const T *)L.r, \
+        k_coarse_tail<T, CF, 0><<<1, kTailBlock, lds, s>>>(L.n, VAL, L.col, L.dcol, L.dbase, ct, (const T *)L.r, \
                                                           (T *)L.z);
     if (fp32) {
-        if (L.dcol) { MG_TAIL(float, L.val32, true) } else { MG_TAIL(float, L.val32, false) }
+        if (L.cf == 2) { MG_TAIL(float, L.val32, 2) } else if (L.cf == 1) { MG_TAIL(float, L.val32, 1) } else { MG_TAIL(float, L.val32, 0) }
     } else {
-        if (L.dcol) { MG_TAIL(double, L.val64, true) } else { MG_TAIL(double, L.val64, false) }
+        if (L.cf == 2) { MG_TAIL(double, L.val64, 2) } else if (L.cf == 1) { MG_TAIL(double, L.val64, 1) } else { MG_TAIL(double, L.val64, 0) }
     }
 #undef MG_TAIL
     return hipGetLastError();
@@ -1107,29 +1119,29 @@ hipError_t launch_coarse_vcycle(const mgpcg_problem *P, bool fp32, hipStream_t s
     const CoarseArgs &A = P->coarse_args;
     const int B = P->coarse_blocks;
     if (P->R != 1 || A.nphases < 1) return hipErrorInvalidValue;
-#define MG_COARSE(T, D8)                                                                               \
-    if (P->colour_order) k_coarse_vcycle<T, 1, D8, 1><<<B, kBlock, 0, s>>>(A);                           \
-    else k_coarse_vcycle<T, 1, D8, 0><<<B, kBlock, 0, s>>>(A);
+#define MG_COARSE(T, CF)                                                                               \
+    if (P->colour_order) k_coarse_vcycle<T, 1, CF, 1><<<B, kBlock, 0, s>>>(A);                           \
+    else k_coarse_vcycle<T, 1, CF, 0><<<B, kBlock, 0, s>>>(A);
     if (fp32) {
-        if (A.d8) { MG_COARSE(float, true) } else { MG_COARSE(float, false) }
+        if (A.cf == 2) { MG_COARSE(float, 2) } else if (A.cf == 1) { MG_COARSE(float, 1) } else { MG_COARSE(float, 0) }
     } else {
-        if (A.d8) { MG_COARSE(double, true) } else { MG_COARSE(double, false) }
+        if (A.cf == 2) { MG_COARSE(double, 2) } else if (A.cf == 1) { MG_COARSE(double, 1) } else { MG_COARSE(double, 0) }
     }
 #undef MG_COARSE
     return hipGetLastError();
 }
 
-int coarse_vcycle_occupancy(int R, bool fp32, bool d8, int order) {
+int coarse_vcycle_occupancy(int R, bool fp32, int cf, int order) {
     if (R != 1) return 0;
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
-#define MG_OCC(T, D8, O) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<T, 1, D8, O>, kBlock, 0);
-#define MG_OCC2(T, D8)                                                                                  \
-    if (order) { MG_OCC(T, D8, 1) } else { MG_OCC(T, D8, 0) }
+#define MG_OCC(T, CF, O) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_coarse_vcycle<T, 1, CF, O>, kBlock, 0);
+#define MG_OCC2(T, CF)                                                                                  \
+    if (order) { MG_OCC(T, CF, 1) } else { MG_OCC(T, CF, 0) }
     if (fp32) {
-        if (d8) { MG_OCC2(float, true) } else { MG_OCC2(float, false) }
+        if (cf == 2) { MG_OCC2(float, 2) } else if (cf == 1) { MG_OCC2(float, 1) } else { MG_OCC2(float, 0) }
     } else {
-        if (d8) { MG_OCC2(double, true) } else { MG_OCC2(double, false) }
+        if (cf == 2) { MG_OCC2(double, 2) } else if (cf == 1) { MG_OCC2(double, 1) } else { MG_OCC2(double, 0) }
     }
 #undef MG_OCC2
 #undef MG_OCC
@@ -1141,7 +1153,7 @@ int coarse_vcycle_occupancy(int R, bool fp32, bool d8, int order) {
 // rc = inject(r - A z): only the injection rows of the residual are formed.
 // Threads walk the injection rows in fine order (coalesced operator reads)
 // and scatter into the coarse vector.
-template <typename T, int R, bool NT, bool D8>
+template <typename T, int R, bool NT, int CF>
 __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restrict__ val,
                                                      const int32_t *__restrict__ col,
                                                      const int8_t *__restrict__ dcol,
@@ -1157,8 +1169,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restr
     int v = (int)(gid % R);
     int64_t i = inj_fine[t];
     T d;
-    const int32_t *sb = D8 ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
-    const T acc = row_sum<T, R, 0u, NT, D8>(val, col, dcol, sb, n, i, z, v, d);
+    const int32_t *sb = CF ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
+    const T acc = row_sum<T, R, 0u, NT, CF>(val, col, dcol, sb, n, i, z, v, d);
     rc[(int64_t)inj_coarse[t] * R + v] = r[i * R + v] - acc;
 }
 
@@ -1169,13 +1181,13 @@ hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, cons
     int64_t work = L.n_inj * P->R;
     if (work == 0) return hipSuccess;
     const CoffTable ct = coff_table(L);
-#define MG_RESTRICT(NT, D8)                                                                             \
-    MG_DISPATCH_R(P->R, (k_restrict<T, RR, NT, D8><<<nblocks(work), kBlock, 0, s>>>(                    \
+#define MG_RESTRICT(NT, CF)                                                                             \
+    MG_DISPATCH_R(P->R, (k_restrict<T, RR, NT, CF><<<nblocks(work), kBlock, 0, s>>>(                    \
                             L.n, val, L.col, L.dcol, L.dbase, ct, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
     if (L.stream_nt) {
-        if (L.dcol) { MG_RESTRICT(true, true) } else { MG_RESTRICT(true, false) }
+        if (L.cf == 2) { MG_RESTRICT(true, 2) } else if (L.cf == 1) { MG_RESTRICT(true, 1) } else { MG_RESTRICT(true, 0) }
     } else {
-        if (L.dcol) { MG_RESTRICT(false, true) } else { MG_RESTRICT(false, false) }
+        if (L.cf == 2) { MG_RESTRICT(false, 2) } else if (L.cf == 1) { MG_RESTRICT(false, 1) } else { MG_RESTRICT(false, 0) }
     }
 #undef MG_RESTRICT
     return hipGetLastError();
@@ -1308,7 +1320,7 @@ __device__ __forceinline__ Seg vec_seg(const Seg *__restrict__ tab, int blk, int
 }
 
 // r = b - A x, partial ||r||^2
-template <int R, bool D8>
+template <int R, int CF>
 __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const double *__restrict__ val,
                                                           const int32_t *__restrict__ col,
                                                           const int8_t *__restrict__ dcol,
@@ -1324,8 +1336,8 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
     if (rl < e.count) {
         const int64_t i = e.row0 + rl;
         double d;
-        const int32_t *sb = D8 ? dbase + e.colour * kW : nullptr;
-        const double s = row_sum<double, R, 0u, true, D8>(val, col, dcol, sb, n, i, x, v, d);
+        const int32_t *sb = CF ? dbase + e.colour * kW : nullptr;
+        const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
         const double ri = b[i * R + v] - s;
         r[i * R + v] = ri;
         acc = ri * ri;
@@ -1385,7 +1397,7 @@ __global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ 
 }
 
 // q = A p, partial <p, q>
-template <int R, bool D8>
+template <int R, int CF>
 __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__restrict__ val,
                                                     const int32_t *__restrict__ col,
                                                     const int8_t *__restrict__ dcol,
@@ -1401,8 +1413,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
     if (rl < e.count) {
         const int64_t i = e.row0 + rl;
         double d;
-        const int32_t *sb = D8 ? dbase + e.colour * kW : nullptr;
-        const double s = row_sum<double, R, 0u, true, D8>(val, col, dcol, sb, n, i, p, v, d);
+        const int32_t *sb = CF ? dbase + e.colour * kW : nullptr;
+        const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
         q[i * R + v] = s;
         acc = p[i * R + v] * s;
     }
@@ -1520,15 +1532,11 @@ static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hi
 // rows per thread (table 1).
 hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
-    if (L.dcol) {
-        MG_DISPATCH_R(P->R, (k_init_residual<RR, true><<<P->n_red[0], kBlock, 0, s>>>(
-                                L.n, L.val64, L.col, L.dcol, L.dbase, P->b, P->x, P->r, P->red_tab[0],
-                                P->sc.partials)));
-    } else {
-        MG_DISPATCH_R(P->R, (k_init_residual<RR, false><<<P->n_red[0], kBlock, 0, s>>>(
-                                L.n, L.val64, L.col, L.dcol, L.dbase, P->b, P->x, P->r, P->red_tab[0],
-                                P->sc.partials)));
-    }
+#define MG_INITR(CFV)                                                                                  \
+    MG_DISPATCH_R(P->R, (k_init_residual<RR, CFV><<<P->n_red[0], kBlock, 0, s>>>(                       \
+                            L.n, L.val64, L.col, L.dcol, L.dbase, P->b, P->x, P->r, P->red_tab[0], P->sc.partials)));
+    if (L.cf == 2) { MG_INITR(2) } else if (L.cf == 1) { MG_INITR(1) } else { MG_INITR(0) }
+#undef MG_INITR
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kInit>(P, 0, 0.0, 0, s);
@@ -1551,15 +1559,12 @@ hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s) {
 }
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
-    if (L.dcol) {
-        MG_DISPATCH_R(P->R, (k_spmv_pq<RR, true><<<P->n_red[0], kBlock, 0, s>>>(
-                                L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials,
-                                P->G == 1 ? nullptr : P->sc.done)));
-    } else {
-        MG_DISPATCH_R(P->R, (k_spmv_pq<RR, false><<<P->n_red[0], kBlock, 0, s>>>(
-                                L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials,
-                                P->G == 1 ? nullptr : P->sc.done)));
-    }
+#define MG_SPMVPQ(CFV)                                                                                 \
+    MG_DISPATCH_R(P->R, (k_spmv_pq<RR, CFV><<<P->n_red[0], kBlock, 0, s>>>(                             \
+                            L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials, \
+                            P->G == 1 ? nullptr : P->sc.done)));
+    if (L.cf == 2) { MG_SPMVPQ(2) } else if (L.cf == 1) { MG_SPMVPQ(1) } else { MG_SPMVPQ(0) }
+#undef MG_SPMVPQ
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kPq>(P, 0, 0.0, 0, s);

@@ -184,7 +184,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         // per-colour column bases for delta-coded columns (single grid):
         // base[k][s] = column - row of the first row of colour k that has a
         // neighbour in slot s
-        if (G == 1 && P->delta_cols) {
+        if (G == 1 && P->col_format >= 1) {
             const LevelGrid &lg = Lv.grids[0];
             std::vector<int32_t> base(8 * kW, 0);
             for (int k = 0; k < Lv.ncol; ++k) {
@@ -333,26 +333,33 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             Lv.z = z64;
         }
         HIP_TRY(launch_build_ell(P, l, theta, s));
+        Lv.cf = 0;
         if (Lv.dbase) {
-            // try the compact column format; keep int32 columns if any delta is out of range
+            // try the compact column formats: implied columns if every delta
+            // is zero, int8 deltas if every delta fits, else int32 columns
             ST_TRY(dalloc(&Lv.dcol, delta_bytes(Lv.n)));
             int64_t *coff_dev = nullptr;
-            int *bad = nullptr;
+            int *flags = nullptr;
             std::vector<int64_t> coffv(Lv.coff.begin(), Lv.coff.end());
             ST_TRY(upload(&coff_dev, coffv, s));
-            ST_TRY(dalloc(&bad, 1));
-            HIP_TRY(launch_fill_i(bad, 1, 0, s));
-            HIP_TRY(launch_delta_encode(P, l, coff_dev, bad, s));
-            int hbad = 1;
-            HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+            ST_TRY(dalloc(&flags, 2));
+            HIP_TRY(launch_fill_i(flags, 2, 0, s));
+            HIP_TRY(launch_delta_encode(P, l, coff_dev, flags, s));
+            int hflags[2] = {1, 1};
+            HIP_TRY(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             dfree(coff_dev);
-            dfree(bad);
-            if (hbad) {
+            dfree(flags);
+            if (hflags[0]) {
                 dfree(Lv.dcol);
                 dfree(Lv.dbase);
             } else {
                 dfree(Lv.col);
+                Lv.cf = 1;
+                if (!hflags[1] && P->col_format >= 2) {
+                    dfree(Lv.dcol);
+                    Lv.cf = 2;
+                }
             }
         }
     }
@@ -452,8 +459,8 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         auto eligible = [&](int from) {
             bool ok = from >= 1 && from < L && R == 1;
             for (int l = from; l < L && ok; ++l) ok = P->lev[l].zs_std && P->lev[l].ncol == 8;
-            const bool d8 = ok && P->lev[from].dcol != nullptr;
-            for (int l = from; l < L && ok; ++l) ok = (P->lev[l].dcol != nullptr) == d8;
+            const int cf = ok ? P->lev[from].cf : 0;
+            for (int l = from; l < L && ok; ++l) ok = P->lev[l].cf == cf;
             return ok;
         };
         // the phase program of the V-cycle of Listing 1 from level `from` down
@@ -479,7 +486,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             }
             if ((int)prog.size() > kMaxPhases) return false;
             memset(&A, 0, sizeof(A));
-            A.d8 = P->lev[from].dcol != nullptr;
+            A.cf = P->lev[from].cf;
             for (int l = from; l < L; ++l) {
                 const Level &Lv = P->lev[l];
                 CoarseLevel &cl = A.lev[l];
@@ -509,7 +516,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         bool ok = eligible(lc);
         int ncu = 0;
         if (ok && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess) ok = false;
-        const int occ = ok ? coarse_vcycle_occupancy(R, fp32, P->lev[lc].dcol != nullptr, P->colour_order) : 0;
+        const int occ = ok ? coarse_vcycle_occupancy(R, fp32, P->lev[lc].cf, P->colour_order) : 0;
         if (ok && occ < 1) ok = false;
         if (ok) ok = program(lc, P->coarse_args);
         if (ok) {
@@ -866,7 +873,8 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     P->mg_dtype = cfg->mg_dtype;
     P->colour_order = cfg->colour_order;
     P->dims0.assign(cfg->dims, cfg->dims + 3 * cfg->ngrids);
-    if (const char *env = getenv("MGPCG_DELTA_COLS")) P->delta_cols = atoi(env) != 0;  // tuning override
+    // tuning and test override: 0 int32 columns, 1 at most int8 deltas, 2 (default) implied columns allowed
+    if (const char *env = getenv("MGPCG_DELTA_COLS")) P->col_format = std::min(2, std::max(0, atoi(env)));
     mgpcg_status st = build_hierarchy(P, cfg->theta, stream);
     if (st != MGPCG_OK) {
         std::string msg = g_err;

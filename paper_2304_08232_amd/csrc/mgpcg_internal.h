@@ -86,6 +86,9 @@ struct Level {
     // the deltas packed four to a word at delta_word(s / 4, i), byte s % 4;
     // used when every real entry's delta fits in int8 (single-grid problems)
     int8_t *dcol = nullptr;
+    // column format: 0 int32 columns (col), 1 int8 deltas (dcol + dbase),
+    // 2 every delta zero, the columns implied by the bases (dbase only)
+    int cf = 0;
     int32_t *dbase = nullptr; // [8][27]
     std::vector<int32_t> dbase_host;
     int32_t *perm = nullptr;  // natural packed row -> internal row
@@ -136,7 +139,7 @@ struct CoarseArgs {
     CoarseLevel lev[MGPCG_MAX_LEVELS];
     int nphases;
     uint16_t phase[kMaxPhases];
-    bool d8;              // every coarse level is delta-coded
+    int cf;               // column format of every coarse level (Level::cf)
     unsigned *flags;       // one per workgroup
     unsigned *epoch_base;  // advanced by the kernel at each launch
     int *err;              // set when a barrier wait times out
@@ -157,7 +160,9 @@ struct mgpcg_problem {
     int G = 1, R = 1, S = 1, L = 1;
     int mg_dtype = MGPCG_FP64;
     int colour_order = 0;
-    bool delta_cols = true;  // allow int8 delta-coded columns (single-grid problems)
+    // most compact column format allowed (Level::cf): 2 by default; single
+    // grids only use the delta formats
+    int col_format = 2;
     std::vector<int> dims0;  // 3*G, level 0
     std::vector<mg::Level> lev;
 
