@@ -299,16 +299,18 @@ __global__ __launch_bounds__(kBlock) void k_delta_encode(int64_t n, const double
                                                          const int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ base,
                                                          const int64_t *__restrict__ coff, int ncol,
+                                                         const int32_t *__restrict__ grow,
                                                          int8_t *__restrict__ dcol, int *__restrict__ flags) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     bool bad = false, nonzero = false;
     if (i < n) {
         const int k = colour_of(coff, ncol, i);
+        const int32_t *b = base + ((grow ? grow[i] : 0) * 8 + k) * kW;
 #pragma unroll
         for (int s = 0; s < kW; ++s) {
             const int64_t e = ell_index(s, i);
             const bool real = val64 ? val64[e] != 0.0 : val32[e] != 0.0f;
-            int64_t dlt = real ? (int64_t)col[e] - i - base[k * kW + s] : 0;
+            int64_t dlt = real ? (int64_t)col[e] - i - b[s] : 0;
             nonzero = nonzero || dlt != 0;
             if (dlt < -128 || dlt > 127) {
                 bad = true;
@@ -329,7 +331,7 @@ hipError_t launch_delta_encode(const mgpcg_problem *P, int level, const int64_t 
     const Level &L = P->lev[level];
     if (L.n == 0) return hipSuccess;
     k_delta_encode<<<nblocks(L.n), kBlock, 0, s>>>(L.n, L.val64, L.val32, L.col, L.dbase, coff_dev, L.ncol,
-                                                   L.dcol, flags);
+                                                   L.grid_of_row, L.dcol, flags);
     return hipGetLastError();
 }
 
@@ -383,13 +385,14 @@ hipError_t launch_permute(const mgpcg_problem *P, int level, const double *src, 
 template <typename T, int R, int CF>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
-                                                 const int32_t *__restrict__ dbase, CoffTable ct,
+                                                 const int32_t *__restrict__ dbase,
+                                                 const int32_t *__restrict__ grow, CoffTable ct,
                                                  const T *__restrict__ x, T *__restrict__ y) {
     int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (gid >= n * R) return;
     int64_t i = gid / R;
     int v = (int)(gid % R);
-    const int32_t *sb = CF ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
+    const int32_t *sb = CF ? dbase + ((grow ? grow[i] : 0) * 8 + colour_of(ct.coff, ct.ncol, i)) * kW : nullptr;
     T d;
     y[gid] = row_sum<T, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
 }
@@ -401,8 +404,8 @@ hipError_t launch_spmv(const mgpcg_problem *P, int level, const T *val, const T 
     if (work == 0) return hipSuccess;
     const CoffTable ct = coff_table(L);
 #define MG_SPMV(CFV)                                                                                   \
-    MG_DISPATCH_R(P->R, (k_spmv<T, RR, CFV><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol, L.dbase, ct, \
-                                                                            x, y)));
+    MG_DISPATCH_R(P->R, (k_spmv<T, RR, CFV><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol, L.dbase, \
+                                                                            L.grid_of_row, ct, x, y)));
     if (L.cf == 2) { MG_SPMV(2) } else if (L.cf == 1) { MG_SPMV(1) } else { MG_SPMV(0) }
 #undef MG_SPMV
     return hipGetLastError();
@@ -545,20 +548,27 @@ __device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val,
 template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, bool TWICE = false, bool DOT = false>
 __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__restrict__ val,
                                                  const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
-                                                 const Base27 sb,
+                                                 const Base27 sb_arg,
                                                  const T *__restrict__ r, T *z,
                                                  const Seg *__restrict__ tab, int64_t row_base,
                                                  int64_t row_end, const int *__restrict__ done,
                                                  T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
-                                                 double *__restrict__ rzp) {
+                                                 double *__restrict__ rzp, const int32_t *__restrict__ gbase) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
+    Base27 sb = sb_arg;
     if (tab) {
         const Seg e = tab[b];
         row0 = e.row0;
         count = e.count;
         grid = e.grid;
+        // several grids: the bases of this segment's grid and colour
+        if (CF && gbase) {
+            const int32_t *gb = gbase + (e.grid * 8 + e.colour) * kW;
+#pragma unroll
+            for (int t = 0; t < kW; ++t) sb.v[t] = gb[t];
+        }
     } else {
         row0 = row_base + (int64_t)b * (pass_block(NT) / R);
         count = row_end - row0;
@@ -590,18 +600,25 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
 template <typename T, int R, bool NT, int CF, int ORD>
 __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T *__restrict__ val,
                                                       const int32_t *__restrict__ col,
-                                                      const int8_t *__restrict__ dcol, const Base27 sb1,
+                                                      const int8_t *__restrict__ dcol, const Base27 sb_arg,
                                                       const T *__restrict__ r, T *__restrict__ z,
                                                       const Seg *__restrict__ tab, int64_t coff0, int64_t coff1,
-                                                      int64_t coff2, const int *__restrict__ done) {
+                                                      int64_t coff2, const int *__restrict__ done,
+                                                      const int32_t *__restrict__ gbase) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
+    Base27 sb1 = sb_arg;  // bases of colour 1
     if (tab) {
         const Seg e = tab[b];
         row0 = e.row0;
         count = e.count;
         grid = e.grid;
+        if (CF && gbase) {
+            const int32_t *gb = gbase + (e.grid * 8 + 1) * kW;
+#pragma unroll
+            for (int t = 0; t < kW; ++t) sb1.v[t] = gb[t];
+        }
     } else {
         row0 = coff0 + (int64_t)b * (pass_block(NT) / R);
         count = coff2 - row0;
@@ -650,11 +667,11 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
 template <typename T, int R, bool NT, int CF>
 static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T *val, const int32_t *col,
                     const int8_t *dcol, const Base27 &sb, const T *r, T *z, const Seg *tab, int64_t rb,
-                    int64_t re, const int *done) {
+                    int64_t re, const int *done, const int32_t *gb) {
 #define MG_ZS_CASE(K, O)                                                                              \
     case K + 8 * O:                                                                                   \
         k_pass<T, R, zs_mask(K, O), NT, 0, CF><<<cnt, pass_block(NT), 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
-                                                                      done, nullptr, nullptr, nullptr); \
+                                                                      done, nullptr, nullptr, nullptr, gb); \
         break;
     switch (k + 8 * order) {
         MG_ZS_CASE(0, 0) MG_ZS_CASE(1, 0) MG_ZS_CASE(2, 0) MG_ZS_CASE(3, 0)
@@ -677,6 +694,8 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     const int R = P->R;
     if (rzp && (sizeof(T) != 8 || P->G != 1 || (mode != kPassPlain && mode != kPassTwice)))
         return hipErrorInvalidValue;
+    // several grids: the kernels read each segment's bases from the device table
+    const int32_t *gb = P->G > 1 ? L.dbase : nullptr;
     const Seg *tab = nullptr;
     int cnt;
     const int64_t rb = L.coff[k], re = L.coff[k + 1];
@@ -708,10 +727,10 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
 #define MG_ZS01(RR, NT, CF)                                                                             \
     if (P->colour_order)                                                                               \
         k_pass_zs01<T, RR, NT, CF, 1><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
-                                                            L.coff[0], L.coff[1], L.coff[2], done);      \
+                                                            L.coff[0], L.coff[1], L.coff[2], done, gb);  \
     else                                                                                               \
         k_pass_zs01<T, RR, NT, CF, 0><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
-                                                            L.coff[0], L.coff[1], L.coff[2], done);
+                                                            L.coff[0], L.coff[1], L.coff[2], done, gb);
 #define MG_ZS01_R(NT, CF)                                                                               \
     if (R == 1) { MG_ZS01(1, NT, CF) } else { MG_ZS01(16, NT, CF) }
         if (L.stream_nt) {
@@ -731,10 +750,10 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (rzp && SKIPM == 0u) {                                                                          \
         if constexpr (sizeof(T) == 8)                                                                  \
             MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true, true><<<cnt, pass_block(NT), 0, s>>>(  \
-                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp))); \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp, gb))); \
     } else {                                                                                           \
         MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true><<<cnt, pass_block(NT), 0, s>>>(            \
-                             L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr))); \
+                             L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr, gb))); \
     }
 #define MG_TWICE_MODE(SKIPM)                                                                            \
     if (L.stream_nt) {                                                                                 \
@@ -755,8 +774,8 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         if (!L.zs_std || (R != 1 && R != 16)) return hipErrorInvalidValue;
         const int ord = P->colour_order;
 #define MG_ZS_LAUNCH(NT, CF)                                                                           \
-    if (R == 1) pass_zs<T, 1, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done); \
-    else pass_zs<T, 16, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done);
+    if (R == 1) pass_zs<T, 1, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb); \
+    else pass_zs<T, 16, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb);
         if (L.stream_nt) {
             if (L.cf == 2) { MG_ZS_LAUNCH(true, 2) } else if (L.cf == 1) { MG_ZS_LAUNCH(true, 1) } else { MG_ZS_LAUNCH(true, 0) }
         } else {
@@ -769,11 +788,11 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (M == 0 && rzp) {                                                                               \
         if constexpr (sizeof(T) == 8)                                                                  \
             MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, 0, CF, false, true><<<cnt, pass_block(NT), 0, s>>>(    \
-                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp)));  \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp, gb))); \
     } else {                                                                                           \
         MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, CF><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, \
                                                                           r, z, tab, rb, re, done, coarse, ic, \
-                                                                          nullptr)));             \
+                                                                          nullptr, gb)));         \
     }
 #define MG_PASS_MODE(M)                                                                                \
     if (L.stream_nt) {                                                                                 \
@@ -1157,7 +1176,8 @@ template <typename T, int R, bool NT, int CF>
 __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restrict__ val,
                                                      const int32_t *__restrict__ col,
                                                      const int8_t *__restrict__ dcol,
-                                                     const int32_t *__restrict__ dbase, CoffTable ct,
+                                                     const int32_t *__restrict__ dbase,
+                                                     const int32_t *__restrict__ grow, CoffTable ct,
                                                      const T *__restrict__ r, const T *__restrict__ z,
                                                      T *__restrict__ rc,
                                                      const int32_t *__restrict__ inj_fine,
@@ -1169,7 +1189,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restr
     int v = (int)(gid % R);
     int64_t i = inj_fine[t];
     T d;
-    const int32_t *sb = CF ? dbase + colour_of(ct.coff, ct.ncol, i) * kW : nullptr;
+    const int32_t *sb = CF ? dbase + ((grow ? grow[i] : 0) * 8 + colour_of(ct.coff, ct.ncol, i)) * kW : nullptr;
     const T acc = row_sum<T, R, 0u, NT, CF>(val, col, dcol, sb, n, i, z, v, d);
     rc[(int64_t)inj_coarse[t] * R + v] = r[i * R + v] - acc;
 }
@@ -1183,7 +1203,8 @@ hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, cons
     const CoffTable ct = coff_table(L);
 #define MG_RESTRICT(NT, CF)                                                                             \
     MG_DISPATCH_R(P->R, (k_restrict<T, RR, NT, CF><<<nblocks(work), kBlock, 0, s>>>(                    \
-                            L.n, val, L.col, L.dcol, L.dbase, ct, r, z, rc, L.inj_fine, L.inj_coarse, L.n_inj)));
+                            L.n, val, L.col, L.dcol, L.dbase, L.grid_of_row, ct, r, z, rc, L.inj_fine,          \
+                            L.inj_coarse, L.n_inj)));
     if (L.stream_nt) {
         if (L.cf == 2) { MG_RESTRICT(true, 2) } else if (L.cf == 1) { MG_RESTRICT(true, 1) } else { MG_RESTRICT(true, 0) }
     } else {
@@ -1336,7 +1357,7 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
     if (rl < e.count) {
         const int64_t i = e.row0 + rl;
         double d;
-        const int32_t *sb = CF ? dbase + e.colour * kW : nullptr;
+        const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
         const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
         const double ri = b[i * R + v] - s;
         r[i * R + v] = ri;
@@ -1413,7 +1434,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
     if (rl < e.count) {
         const int64_t i = e.row0 + rl;
         double d;
-        const int32_t *sb = CF ? dbase + e.colour * kW : nullptr;
+        const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
         const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
         q[i * R + v] = s;
         acc = p[i * R + v] * s;

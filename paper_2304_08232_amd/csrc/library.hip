@@ -181,30 +181,43 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(upload(&P->d_natoff[l], natoff, s));
         if (l == 0) ST_TRY(upload(&P->d_natoff0, natoff, s));
 
-        // per-colour column bases for delta-coded columns (single grid):
-        // base[k][s] = column - row of the first row of colour k that has a
-        // neighbour in slot s
-        if (G == 1 && P->col_format >= 1) {
-            const LevelGrid &lg = Lv.grids[0];
-            std::vector<int32_t> base(8 * kW, 0);
-            for (int k = 0; k < Lv.ncol; ++k) {
-                int missing = kW;
-                std::vector<char> have(kW, 0);
-                for (int64_t i = Lv.coff[k]; i < Lv.coff[k + 1] && missing > 0; ++i) {
-                    const int64_t q = iperm[i];
-                    const int ix = (int)(q % lg.nx), iy = (int)((q / lg.nx) % lg.ny), iz = (int)(q / ((int64_t)lg.nx * lg.ny));
-                    for (int sl = 0; sl < kW; ++sl) {
-                        if (have[sl]) continue;
-                        const int jx = ix + sl % 3 - 1, jy = iy + (sl / 3) % 3 - 1, jz = iz + sl / 9 - 1;
-                        if (jx < 0 || jx >= lg.nx || jy < 0 || jy >= lg.ny || jz < 0 || jz >= lg.nz) continue;
-                        base[k * kW + sl] = (int32_t)(perm[jx + (int64_t)lg.nx * (jy + (int64_t)lg.ny * jz)] - i);
-                        have[sl] = 1;
-                        --missing;
+        // column bases for the compact column formats, per grid and colour:
+        // base[g][k][s] = column - row of the first row of colour k of grid g
+        // that has a neighbour in slot s
+        if (P->col_format >= 1) {
+            std::vector<int32_t> base((size_t)G * 8 * kW, 0);
+            for (int g = 0; g < G; ++g) {
+                const LevelGrid &lg = Lv.grids[g];
+                const int64_t no = natoff[g];
+                for (int k = 0; k < Lv.ncol; ++k) {
+                    int missing = kW;
+                    std::vector<char> have(kW, 0);
+                    for (int64_t i = lg.seg_off[k]; i < lg.seg_off[k] + lg.seg_len[k] && missing > 0; ++i) {
+                        const int64_t q = iperm[i] - no;
+                        const int ix = (int)(q % lg.nx), iy = (int)((q / lg.nx) % lg.ny),
+                                  iz = (int)(q / ((int64_t)lg.nx * lg.ny));
+                        for (int sl = 0; sl < kW; ++sl) {
+                            if (have[sl]) continue;
+                            const int jx = ix + sl % 3 - 1, jy = iy + (sl / 3) % 3 - 1, jz = iz + sl / 9 - 1;
+                            if (jx < 0 || jx >= lg.nx || jy < 0 || jy >= lg.ny || jz < 0 || jz >= lg.nz) continue;
+                            base[((size_t)g * 8 + k) * kW + sl] =
+                                (int32_t)(perm[no + jx + (int64_t)lg.nx * (jy + (int64_t)lg.ny * jz)] - i);
+                            have[sl] = 1;
+                            --missing;
+                        }
                     }
                 }
             }
             ST_TRY(upload(&Lv.dbase, base, s));
             Lv.dbase_host = base;
+            if (G > 1) {
+                // grid of each internal row, for the kernels that index rows directly
+                std::vector<int32_t> grow(Lv.n);
+                for (int g = 0; g < G; ++g)
+                    for (int k = 0; k < Lv.ncol; ++k)
+                        for (int64_t i = 0; i < Lv.grids[g].seg_len[k]; ++i) grow[Lv.grids[g].seg_off[k] + i] = g;
+                ST_TRY(upload(&Lv.grid_of_row, grow, s));
+            }
         }
 
         const int64_t opbytes = Lv.n * kW * ((P->mg_dtype == MGPCG_FP32 && l > 0 ? 4 : 8) + 4);
@@ -461,6 +474,8 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             for (int l = from; l < L && ok; ++l) ok = P->lev[l].zs_std && P->lev[l].ncol == 8;
             const int cf = ok ? P->lev[from].cf : 0;
             for (int l = from; l < L && ok; ++l) ok = P->lev[l].cf == cf;
+            // its phases index rows directly: compact columns only for one grid
+            if (G > 1 && cf != 0) ok = false;
             return ok;
         };
         // the phase program of the V-cycle of Listing 1 from level `from` down
@@ -549,7 +564,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         bool fits = true;
         for (int k = 0; k < Lt.ncol; ++k) fits = fits && Lt.coff[k + 1] - Lt.coff[k] <= kTailBlock;
         P->tail_ok = L >= 2 && R == 1 && Lt.zs_std && Lt.ncol == 8 && need <= tail_bytes &&
-                     need <= (64 << 10) && fits;
+                     need <= (64 << 10) && fits && (G == 1 || Lt.cf == 0);
         P->tail_lw = P->tail_ok ? L - 1 : L;
     }
     HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int), hipHostMallocDefault));
@@ -566,6 +581,7 @@ void free_problem(mgpcg_problem *P) {
     (void)hipDeviceSynchronize();
     for (auto &Lv : P->lev) {
         dfree(Lv.val64); dfree(Lv.val32); dfree(Lv.col); dfree(Lv.dcol); dfree(Lv.dbase); dfree(Lv.perm);
+        dfree(Lv.grid_of_row);
         dfree(Lv.iperm);
         dfree(Lv.grid_of_nat); dfree(Lv.pass_tab); dfree(Lv.inj_fine); dfree(Lv.inj_coarse);
         dfree(Lv.r); dfree(Lv.z); dfree(Lv.t0); dfree(Lv.t1); dfree(Lv.t2);

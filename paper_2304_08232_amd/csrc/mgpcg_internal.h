@@ -82,14 +82,15 @@ struct Level {
     double *val64 = nullptr;  // at ell_index(s, i): FP64 operator (level 0 always; all levels if FP64 V-cycle)
     float *val32 = nullptr;   // at ell_index(s, i): FP32 operator (FP32 V-cycle)
     int32_t *col = nullptr;   // at ell_index(s, i): absolute columns (NULL when delta-coded)
-    // delta-coded columns: col(i,s) = i + dbase[colour(i)*27 + s] + delta(s, i),
+    // delta-coded columns: col(i,s) = i + dbase[grid(i)][colour(i)][s] + delta(s, i),
     // the deltas packed four to a word at delta_word(s / 4, i), byte s % 4;
-    // used when every real entry's delta fits in int8 (single-grid problems)
+    // used when every real entry's delta fits in int8
     int8_t *dcol = nullptr;
     // column format: 0 int32 columns (col), 1 int8 deltas (dcol + dbase),
     // 2 every delta zero, the columns implied by the bases (dbase only)
     int cf = 0;
-    int32_t *dbase = nullptr; // [8][27]
+    int32_t *dbase = nullptr; // [G][8][27] column bases (compact formats)
+    int32_t *grid_of_row = nullptr;  // internal row -> grid (G > 1, compact formats)
     std::vector<int32_t> dbase_host;
     int32_t *perm = nullptr;  // natural packed row -> internal row
     int32_t *iperm = nullptr; // internal row -> natural packed row
