@@ -1081,33 +1081,61 @@ __global__ __launch_bounds__(kTailBlock) void k_coarse_tail(int64_t n, const T *
     const ConstBases tb = (ConstBases)dbase;
     T *rs = (T *)tail_lds;
     T *zs = rs + n;
-    RawRow<T, CF> b0, b1;
-    tail_load<T, CF, zs_mask(0, ORD)>(val, col, dcol, ct, 0, b0);
-    for (int64_t i = threadIdx.x; i < n; i += kTailBlock) rs[i] = r[i];
-    __syncthreads();
     // forward, zero start (colour k reads only colours < k); colour 7 is the
-    // last forward and the first backward pass in one; then backward 6..0.
-    // Pass p computes from buffer p % 2 while buffer (p+1) % 2 is refilled.
-#define MG_TAIL_STEP(K, SK, TW, BC, KN, SKN, BN)                                                        \
-    tail_load<T, CF, SKN>(val, col, dcol, ct, KN, BN);                                                 \
-    tail_pass<T, CF, SK, TW>(tb, ct, K, BC, rs, zs);                                                   \
+    // last forward and the first backward pass in one; then backward 6..0:
+    // 15 passes.  Rows of a pass are loaded DEPTH-1 passes ahead: pass p
+    // computes from buffer p % DEPTH while later passes' rows are in flight.
+    // Three buffers in FP32; in FP64 three rows of 27 values no longer fit
+    // in registers next to the working set, so two.
+    constexpr int DEPTH = sizeof(T) == 4 ? 3 : 2;
+#define MG_TAIL_LOAD(K, SK, B) tail_load<T, CF, SK>(val, col, dcol, ct, K, B);
+#define MG_TAIL_PASS(K, SK, TW, B)                                                                      \
+    tail_pass<T, CF, SK, TW>(tb, ct, K, B, rs, zs);                                                    \
     lds_barrier();
-    MG_TAIL_STEP(0, zs_mask(0, ORD), false, b0, 1, zs_mask(1, ORD), b1)
-    MG_TAIL_STEP(1, zs_mask(1, ORD), false, b1, 2, zs_mask(2, ORD), b0)
-    MG_TAIL_STEP(2, zs_mask(2, ORD), false, b0, 3, zs_mask(3, ORD), b1)
-    MG_TAIL_STEP(3, zs_mask(3, ORD), false, b1, 4, zs_mask(4, ORD), b0)
-    MG_TAIL_STEP(4, zs_mask(4, ORD), false, b0, 5, zs_mask(5, ORD), b1)
-    MG_TAIL_STEP(5, zs_mask(5, ORD), false, b1, 6, zs_mask(6, ORD), b0)
-    MG_TAIL_STEP(6, zs_mask(6, ORD), false, b0, 7, zs_mask(7, ORD), b1)
-    MG_TAIL_STEP(7, zs_mask(7, ORD), true, b1, 6, 0u, b0)
-    MG_TAIL_STEP(6, 0u, false, b0, 5, 0u, b1)
-    MG_TAIL_STEP(5, 0u, false, b1, 4, 0u, b0)
-    MG_TAIL_STEP(4, 0u, false, b0, 3, 0u, b1)
-    MG_TAIL_STEP(3, 0u, false, b1, 2, 0u, b0)
-    MG_TAIL_STEP(2, 0u, false, b0, 1, 0u, b1)
-    MG_TAIL_STEP(1, 0u, false, b1, 0, 0u, b0)
-#undef MG_TAIL_STEP
-    tail_pass<T, CF, 0u, false>(tb, ct, 0, b0, rs, zs);
+    if constexpr (DEPTH == 3) {
+        RawRow<T, CF> b0, b1, b2;
+        MG_TAIL_LOAD(0, zs_mask(0, ORD), b0)
+        MG_TAIL_LOAD(1, zs_mask(1, ORD), b1)
+        for (int64_t i = threadIdx.x; i < n; i += kTailBlock) rs[i] = r[i];
+        __syncthreads();
+        MG_TAIL_LOAD(2, zs_mask(2, ORD), b2) MG_TAIL_PASS(0, zs_mask(0, ORD), false, b0)
+        MG_TAIL_LOAD(3, zs_mask(3, ORD), b0) MG_TAIL_PASS(1, zs_mask(1, ORD), false, b1)
+        MG_TAIL_LOAD(4, zs_mask(4, ORD), b1) MG_TAIL_PASS(2, zs_mask(2, ORD), false, b2)
+        MG_TAIL_LOAD(5, zs_mask(5, ORD), b2) MG_TAIL_PASS(3, zs_mask(3, ORD), false, b0)
+        MG_TAIL_LOAD(6, zs_mask(6, ORD), b0) MG_TAIL_PASS(4, zs_mask(4, ORD), false, b1)
+        MG_TAIL_LOAD(7, zs_mask(7, ORD), b1) MG_TAIL_PASS(5, zs_mask(5, ORD), false, b2)
+        MG_TAIL_LOAD(6, 0u, b2) MG_TAIL_PASS(6, zs_mask(6, ORD), false, b0)
+        MG_TAIL_LOAD(5, 0u, b0) MG_TAIL_PASS(7, zs_mask(7, ORD), true, b1)
+        MG_TAIL_LOAD(4, 0u, b1) MG_TAIL_PASS(6, 0u, false, b2)
+        MG_TAIL_LOAD(3, 0u, b2) MG_TAIL_PASS(5, 0u, false, b0)
+        MG_TAIL_LOAD(2, 0u, b0) MG_TAIL_PASS(4, 0u, false, b1)
+        MG_TAIL_LOAD(1, 0u, b1) MG_TAIL_PASS(3, 0u, false, b2)
+        MG_TAIL_LOAD(0, 0u, b2) MG_TAIL_PASS(2, 0u, false, b0)
+        MG_TAIL_PASS(1, 0u, false, b1)
+        tail_pass<T, CF, 0u, false>(tb, ct, 0, b2, rs, zs);
+    } else {
+        RawRow<T, CF> b0, b1;
+        MG_TAIL_LOAD(0, zs_mask(0, ORD), b0)
+        for (int64_t i = threadIdx.x; i < n; i += kTailBlock) rs[i] = r[i];
+        __syncthreads();
+        MG_TAIL_LOAD(1, zs_mask(1, ORD), b1) MG_TAIL_PASS(0, zs_mask(0, ORD), false, b0)
+        MG_TAIL_LOAD(2, zs_mask(2, ORD), b0) MG_TAIL_PASS(1, zs_mask(1, ORD), false, b1)
+        MG_TAIL_LOAD(3, zs_mask(3, ORD), b1) MG_TAIL_PASS(2, zs_mask(2, ORD), false, b0)
+        MG_TAIL_LOAD(4, zs_mask(4, ORD), b0) MG_TAIL_PASS(3, zs_mask(3, ORD), false, b1)
+        MG_TAIL_LOAD(5, zs_mask(5, ORD), b1) MG_TAIL_PASS(4, zs_mask(4, ORD), false, b0)
+        MG_TAIL_LOAD(6, zs_mask(6, ORD), b0) MG_TAIL_PASS(5, zs_mask(5, ORD), false, b1)
+        MG_TAIL_LOAD(7, zs_mask(7, ORD), b1) MG_TAIL_PASS(6, zs_mask(6, ORD), false, b0)
+        MG_TAIL_LOAD(6, 0u, b0) MG_TAIL_PASS(7, zs_mask(7, ORD), true, b1)
+        MG_TAIL_LOAD(5, 0u, b1) MG_TAIL_PASS(6, 0u, false, b0)
+        MG_TAIL_LOAD(4, 0u, b0) MG_TAIL_PASS(5, 0u, false, b1)
+        MG_TAIL_LOAD(3, 0u, b1) MG_TAIL_PASS(4, 0u, false, b0)
+        MG_TAIL_LOAD(2, 0u, b0) MG_TAIL_PASS(3, 0u, false, b1)
+        MG_TAIL_LOAD(1, 0u, b1) MG_TAIL_PASS(2, 0u, false, b0)
+        MG_TAIL_LOAD(0, 0u, b0) MG_TAIL_PASS(1, 0u, false, b1)
+        tail_pass<T, CF, 0u, false>(tb, ct, 0, b0, rs, zs);
+    }
+#undef MG_TAIL_PASS
+#undef MG_TAIL_LOAD
     __syncthreads();
     for (int64_t i = threadIdx.x; i < n; i += kTailBlock) z[i] = zs[i];
 }
@@ -1489,7 +1517,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const int *__restrict__ gb,
     if (KIND != kInit && grid_done<R>(sc.done, g)) return;
     const int v = threadIdx.x % R;
     const int b0 = gb[g], b1 = gb[g + 1];
-    constexpr int kStep = kBlock / R, kU = 8;
+    // all loads of a thread in one round trip for up to 32 partials per thread
+    constexpr int kStep = kBlock / R, kU = 32;
     double s = 0.0;
     for (int b = b0 + threadIdx.x / R; b < b1; b += kU * kStep) {
         double t[kU];
