@@ -161,8 +161,7 @@ struct mgpcg_problem {
     int G = 1, R = 1, S = 1, L = 1;
     int mg_dtype = MGPCG_FP64;
     int colour_order = 0;
-    // most compact column format allowed (Level::cf): 2 by default; single
-    // grids only use the delta formats
+    // most compact column format allowed (Level::cf), 2 by default
     int col_format = 2;
     std::vector<int> dims0;  // 3*G, level 0
     std::vector<mg::Level> lev;
