@@ -79,9 +79,11 @@ typedef struct {
 /* Sec. II-A/B, II-D, III-A: build the level hierarchy on the current device:
  * per level the 27-point operator (diagonal 26, off-diagonals -1 for every
  * in-grid neighbour), its greedy colouring, and the injection maps.  The
- * operator is stored as 27-slot ELL with FP64 (and/or FP32) values and int32
- * column indices, rows grouped by colour.  Synchronises the stream before
- * returning.  *out receives the handle (NULL on failure). */
+ * operator is stored as 27-slot ELL with FP64 (and/or FP32) values, rows
+ * grouped by colour; each level keeps its column indices in the most compact
+ * exact form: implied by per-colour offsets, int8 deltas against them, or
+ * int32 indices.  Synchronises the stream before returning.  *out receives
+ * the handle (NULL on failure). */
 mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_problem **out);
 
 /* Releases every device buffer of the handle.  NULL is accepted. */
@@ -190,9 +192,10 @@ mgpcg_status mgpcg_set_graph_mode(mgpcg_problem *p, int on);
 /* Execution of the coarse levels of the V-cycle: mode 0 (default) launches
  * one kernel per colour pass; mode 1 runs levels 1..L-1 of each V-cycle in
  * one persistent launch whose workgroups separate the phases with a grid
- * barrier (used when nrhs is 1 and every coarse grid has the standard
- * 8-colour numbering; otherwise mode 0 runs).  Results are identical either
- * way. */
+ * barrier (used when nrhs is 1, every coarse grid has the standard 8-colour
+ * numbering and the coarse levels share one column format, int32 when the
+ * problem has several grids; otherwise mode 0 runs).  Results are identical
+ * either way. */
 mgpcg_status mgpcg_set_coarse_mode(mgpcg_problem *p, int mode);
 
 /* Synchronises the stream and reports a device-side failure of earlier

@@ -1,12 +1,13 @@
 // gfx950 kernels of the MG-PCG hot path.
 //
-// Every kernel is HBM-bound (about 0.16 flop per byte), so the design goals
-// are: stream the ELL operator exactly once per pass with coalesced,
-// non-temporal loads; keep the vectors (which fit in the Infinity Cache) in
-// the cache hierarchy; hand each XCD a contiguous range of rows so that the
-// neighbour gathers of one XCD hit its own L2; and make every reduction
-// deterministic (fixed-shape wave/LDS trees plus an ordered final pass in the
-// last workgroup of each grid).
+// Every kernel is bound by HBM bandwidth (about 0.16 flop per byte) or, on the
+// small levels, by latency.  The design goals: stream the ELL operator once
+// per pass in wavefront-contiguous blocks (non-temporal loads on levels larger
+// than the caches) with the column data as compact as the level allows; issue
+// a row's neighbour gathers as soon as its columns are known; hand each XCD a
+// contiguous range of rows so that its gathers hit its own L2; and make every
+// reduction deterministic (fixed-shape wave/LDS trees, then a one-workgroup
+// finalize per grid that sums the partials in a fixed order).
 //
 // Floating-point contraction is disabled for this library, so that the
 // per-row arithmetic is exactly the sequence of IEEE operations the method
@@ -26,11 +27,6 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     int per = nb / kXcd, rem = nb % kXcd;
     int x = b % kXcd, q = b / kXcd;
     return x * per + (x < rem ? x : rem) + q;
-}
-
-template <typename T>
-__device__ __forceinline__ T ld_nt(const T *p) {
-    return __builtin_nontemporal_load(p);
 }
 
 __device__ __forceinline__ double softplus_d(double t) {
@@ -154,8 +150,8 @@ __device__ __forceinline__ void decode_cols(const RawRow<T, CF> &rw, const SB &s
 
 // Operator values a[s] and absolute columns c[s] of the 27 slots of row i.
 // All value and column loads of the row are issued before anything uses
-// them, so a wave keeps 34 streaming loads (27 with 32-bit columns: 54) in
-// flight, and then its 27 gathers.
+// them: 27 value loads plus 7 delta words (int8 deltas), 27 columns (int32),
+// or none (implied columns, whose gathers can then leave at once).
 template <typename T, int R, uint32_t SKIP, bool NT, int CF, class SB>
 __device__ __forceinline__ void load_slots(const T *__restrict__ val, const int32_t *__restrict__ col,
                                            const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
@@ -196,10 +192,8 @@ __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_
 }
 
 // sum_j a_ij x_j over the 27 slots of row i, in slot order (ascending natural
-// column order), skipping padding slots (value 0).  All value and column
-// loads of the row are issued before the dependent gathers, so a wave keeps
-// 54 streaming loads and then 27 gathers in flight.  Slots whose bit is set
-// in the compile-time SKIP mask are left out entirely (their x is known to be
+// column order), skipping padding slots (value 0).  Slots whose bit is set in
+// the compile-time SKIP mask are left out entirely (their x is known to be
 // zero); the diagonal value is always loaded and returned in d.
 template <typename T, int R, uint32_t SKIP, bool NT, int CF>
 __device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *__restrict__ col,

@@ -7,10 +7,12 @@
 //   consecutive points along x, so the neighbour in a fixed stencil direction
 //   of consecutive rows is again consecutive: every gather of the sweep reads
 //   near-contiguous memory.
-//   The operator is 27-slot ELL, slot-major: value and column of slot s of row
-//   i at [s*n + i]; slot s is direction (dx,dy,dz) = (s%3-1, s/3%3-1, s/9-1),
-//   i.e. ascending natural column order; slot 13 is the diagonal; a missing
-//   neighbour is a padding slot with value 0 and column i.
+//   The operator is 27-slot ELL, blocked by wavefront (ell_index below):
+//   slot s is direction (dx,dy,dz) = (s%3-1, s/3%3-1, s/9-1), i.e. ascending
+//   natural column order; slot 13 is the diagonal; a missing neighbour is a
+//   padding slot with value 0.  Columns are stored in one of three formats
+//   (Level::cf): int32, int8 deltas against per-colour bases, or implied by
+//   the bases alone.
 //   Vectors with R right-hand sides are interleaved: element (row i, rhs v) at
 //   i*R + v.
 #pragma once
