@@ -266,7 +266,7 @@ def main():
         "us_per_iteration": round(t_step / ITERS * 1e6, 2),
         "final_relres": float(hist[-1]),
         "stream_copy_gbs": round(copy_gbs, 1),
-        "roofline": {"bound": "hbm", "kernel": "k_pass<double, 1, 0u, true, 0, true, false, false> (level-0 colour pass)",
+        "roofline": {"bound": "hbm", "kernel": "k_pass<double, 1, 0u, true, 0, 2, false, false> (level-0 colour pass)",
                      "achieved": round(achieved, 1), "peak": perfmodel.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / perfmodel.HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(per_launch_bytes),
