@@ -12,7 +12,8 @@ Also reported on the same line:
                 events on the stream it runs on, against 8 TB/s;
   cpu_baseline  the CPU oracle (single thread) on a bounded sample;
   extensions    FP32-V-cycle vs FP64 to 1e-9 at 192^3, 64 batched uneven
-                grids and 16 right-hand sides vs one-at-a-time solves.
+                grids and 16 right-hand sides vs one-at-a-time solves, and
+                both colour numberings to 1e-9 at 64^3 and 128^3.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extensions]
        [--no-cpu-baseline] [--only-kernel]
@@ -186,6 +187,27 @@ def extensions(torch, mg):
         "iters": [int(v) for v in itm], "iters_match_single": bool(list(map(int, itm)) == its_single),
         "all_converged": bool(stm == mg.OK)}
     log("multi-rhs:", {k: v for k, v in ext["multi_rhs_16_128cubed"].items() if k != "iters"})
+    del B
+    torch.cuda.empty_cache()
+
+    # colour numbering: order 0 (greedy as found) leaves the coarse correction
+    # with nothing to correct (the restricted residual is zero up to
+    # rounding); order 1 (reversed) makes the coarse levels count
+    ext["colour_order"] = {}
+    for dims, seed in (((64, 64, 64), 7), ((128, 128, 128), 8)):
+        n = dims[0] * dims[1] * dims[2]
+        bo = torch.tensor(inputs.uniform(seed, n), device="cuda")
+        row = {}
+        for order in (0, 1):
+            po = mg.Problem(dims, levels=LEVELS, colour_order=order)
+            to, (xo, ho, ito, sto) = time_to_tol(torch, po, bo, 1e-9)
+            po.close()
+            row[f"order{order}_iters"] = int(ito[0])
+            row[f"order{order}_s"] = round(to, 5)
+            row[f"order{order}_converged"] = bool(sto == mg.OK)
+        row["time_ratio_order1_vs_order0"] = round(row["order1_s"] / row["order0_s"], 3)
+        ext["colour_order"][f"{dims[0]}cubed_uniform_rhs"] = row
+        log("colour order:", dims, row)
     return ext
 
 
