@@ -330,20 +330,50 @@ void ora_prolong_add(const ora_hier *h, int level, const double *zc, double *z) 
  * smoothing pass before and after the coarse correction; on the coarsest
  * level only the pre-smoothing pass runs.
  */
-void ora_vcycle(const ora_hier *h, int level, const double *r, double *z) {
+/*
+ * Sec. II-E, Eq. (1): the sequential symmetric Gauss-Seidel smoother that the
+ * coloured one stands in for.  The forward sweep solves equation i for z_i
+ * in increasing natural index, each update seeing every z_j already updated
+ * in this sweep; the backward sweep does the same in decreasing index.  The
+ * sum of Eq. (1) runs over the off-diagonal entries of row i in ascending
+ * column order.
+ */
+static void gs_row(const ora_level *L, int64_t i, const double *r, double *z) {
+    double acc = 0.0;
+    for (int64_t e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e)
+        if (L->col[e] != i) acc += L->val[e] * z[L->col[e]];
+    z[i] = (r[i] - acc) / L->diag[i];
+}
+
+void ora_sgs_lex(const ora_hier *h, int level, const double *r, double *z) {
+    const ora_level *L = &h->lev[level];
+    for (int64_t i = 0; i < L->n; ++i) gs_row(L, i, r, z);
+    for (int64_t i = L->n - 1; i >= 0; --i) gs_row(L, i, r, z);
+}
+
+/* Listing 1 with the smoother chosen by `lex` (0: coloured, 1: sequential). */
+static void vcycle_with(const ora_hier *h, int level, const double *r, double *z, int lex) {
     const ora_level *L = &h->lev[level];
     memset(z, 0, (size_t)L->n * sizeof(double));
-    ora_sgs(h, level, r, z);
+    if (lex) ora_sgs_lex(h, level, r, z); else ora_sgs(h, level, r, z);
     if (level == h->levels - 1) return;
     const ora_level *C = &h->lev[level + 1];
     double *rc = (double *)xcalloc((size_t)C->n, sizeof(double));
     double *zc = (double *)xcalloc((size_t)C->n, sizeof(double));
     ora_restrict(h, level, r, z, rc);
-    ora_vcycle(h, level + 1, rc, zc);
+    vcycle_with(h, level + 1, rc, zc, lex);
     ora_prolong_add(h, level, zc, z);
-    ora_sgs(h, level, r, z);
+    if (lex) ora_sgs_lex(h, level, r, z); else ora_sgs(h, level, r, z);
     free(rc);
     free(zc);
+}
+
+void ora_vcycle(const ora_hier *h, int level, const double *r, double *z) {
+    vcycle_with(h, level, r, z, 0);
+}
+
+void ora_vcycle_lex(const ora_hier *h, int level, const double *r, double *z) {
+    vcycle_with(h, level, r, z, 1);
 }
 
 /* ------------------------------------------------------------ FP32 kernels */
@@ -437,6 +467,7 @@ int ora_pcg(const ora_hier *h, const double *b, double *x, int max_iters,
     for (k = 1; k <= max_iters; ++k) {
         if (precond == 1) ora_vcycle(h, 0, r, z);
         else if (precond == 2) ora_vcycle32(h, r, z);
+        else if (precond == 3) ora_vcycle_lex(h, 0, r, z);
         else memcpy(z, r, (size_t)n * sizeof(double));
         double rho = ora_dot(n, r, z);
         if (k == 1) {

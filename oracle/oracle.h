@@ -74,14 +74,20 @@ void ora_restrict(const ora_hier *h, int level, const double *r, const double *z
 void ora_prolong_add(const ora_hier *h, int level, const double *zc, double *z);
 void ora_vcycle(const ora_hier *h, int level, const double *r, double *z);
 
+/* Sequential symmetric Gauss-Seidel (Sec. II-E, Eq. (1)): rows in increasing,
+ * then decreasing natural order; and the V-cycle that uses it as smoother. */
+void ora_sgs_lex(const ora_hier *h, int level, const double *r, double *z);
+void ora_vcycle_lex(const ora_hier *h, int level, const double *r, double *z);
+
 /* FP32 V-cycle (project extension): r is rounded to FP32, the whole V-cycle
  * runs in FP32 with FP32 matrix values, z is widened back to FP64. */
 void ora_vcycle32(const ora_hier *h, const double *r, double *z);
 void ora_sgs32(const ora_hier *h, int level, const float *r, float *z);
 
 /* Preconditioned CG (Sec. II-C).  precond: 0 none, 1 FP64 V-cycle,
- * 2 FP32 V-cycle.  x holds x0 on entry and the iterate on exit.  history gets
- * ||r_k||/||r_0|| for k = 1..iters.  tol > 0 stops once history <= tol.
+ * 2 FP32 V-cycle, 3 FP64 V-cycle with the sequential smoother.  x holds x0
+ * on entry and the iterate on exit.  history gets ||r_k||/||r_0|| for
+ * k = 1..iters.  tol > 0 stops once history <= tol.
  * Returns 0 on success, 1 if max_iters was reached with tol > 0 unmet,
  * -5 on breakdown (<p,Ap> not finite or not positive). */
 int ora_pcg(const ora_hier *h, const double *b, double *x, int max_iters,

@@ -39,6 +39,8 @@ def lib():
         L.ora_restrict.argtypes = [vp, i32, vp, vp, vp]
         L.ora_prolong_add.argtypes = [vp, i32, vp, vp]
         L.ora_vcycle.argtypes = [vp, i32, vp, vp]
+        L.ora_sgs_lex.argtypes = [vp, i32, vp, vp]
+        L.ora_vcycle_lex.argtypes = [vp, i32, vp, vp]
         L.ora_vcycle32.argtypes = [vp, vp, vp]
         L.ora_sgs32.argtypes = [vp, i32, vp, vp]
         L.ora_pcg.restype = i32
@@ -165,6 +167,19 @@ class Oracle:
         r = _f64(r)
         z = np.zeros(self.n(level))
         lib().ora_vcycle(self._h, level, _p(r), _p(z))
+        return z
+
+    def sgs_lex(self, r, z, level=0):
+        """Sequential symmetric Gauss-Seidel (Eq. (1), natural row order)."""
+        r = _f64(r)
+        z = _f64(z).copy()
+        lib().ora_sgs_lex(self._h, level, _p(r), _p(z))
+        return z
+
+    def vcycle_lex(self, r, level=0):
+        r = _f64(r)
+        z = np.zeros(self.n(level))
+        lib().ora_vcycle_lex(self._h, level, _p(r), _p(z))
         return z
 
     def vcycle32(self, r):

@@ -248,6 +248,97 @@ def test_restricted_residual_vanishes_under_literal_order():
         assert np.linalg.norm(rc1) >= 1e-3 * np.linalg.norm(r[o1.f2c(lvl)])
 
 
+# ------------------------------------ sequential smoother (Sec. II-E, Eq. (1))
+
+LEX_DIMS = [(2, 2, 2), (5, 3, 2), (6, 5, 4), (7, 1, 3), (1, 1, 1)]
+
+
+@pytest.mark.parametrize("dims", LEX_DIMS)
+def test_lex_sweep_equals_sequential_gs(dims):
+    rng = np.random.default_rng(21)
+    n = dims[0] * dims[1] * dims[2]
+    theta = rng.normal(0, 2, n)
+    o = Oracle(*dims, levels=1, theta=theta)
+    A = bf.dense_stencil(*dims, theta=theta)
+    r, z0 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    order = np.arange(n)
+    ref = bf.gs_sequential(A, r, bf.gs_sequential(A, r, z0, order), order[::-1])
+    np.testing.assert_allclose(o.sgs_lex(r, z0), ref, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("dims", [(5, 3, 2), (6, 5, 4)])
+def test_lex_sweep_from_zero_is_the_sgs_splitting(dims):
+    # from z = 0 the two sweeps apply M^{-1} with M = (D + L) D^{-1} (D + U),
+    # L and U the strict triangles of A in natural order
+    rng = np.random.default_rng(22)
+    o = Oracle(*dims, levels=1)
+    A = o.dense()
+    D = np.diag(np.diag(A))
+    M = (D + np.tril(A, -1)) @ np.linalg.inv(D) @ (D + np.triu(A, 1))
+    r = rng.uniform(-1, 1, o.n())
+    np.testing.assert_allclose(o.sgs_lex(r, np.zeros(o.n())), np.linalg.solve(M, r), rtol=1e-12, atol=1e-14)
+
+
+def test_lex_sweep_fixed_point_and_energy_decrease():
+    rng = np.random.default_rng(23)
+    o = Oracle(6, 5, 4, levels=1)
+    A = o.dense()
+    zs = rng.uniform(-1, 1, o.n())
+    r = A @ zs
+    np.testing.assert_allclose(o.sgs_lex(r, zs), zs, rtol=0, atol=1e-14)
+    # Gauss-Seidel on an SPD matrix strictly reduces the error in the A-norm
+    z = rng.uniform(-1, 1, o.n())
+    for _ in range(3):
+        e0 = z - zs
+        z = o.sgs_lex(r, z)
+        e1 = z - zs
+        assert e1 @ A @ e1 < e0 @ A @ e0
+
+
+@pytest.mark.parametrize("dims,levels", [((4, 4, 4), 3), ((8, 8, 4), 3), ((8, 8, 8), 4)])
+def test_lex_vcycle_equals_dense_bruteforce(dims, levels):
+    # one colour holding every row in natural order is exactly the sequential
+    # smoother in the brute-force V-cycle
+    rng = np.random.default_rng(24)
+    o = Oracle(*dims, levels=levels)
+    As, _, Rs = _dense_hierarchy(o)
+    cs = [np.zeros(o.n(l), dtype=np.int64) for l in range(levels)]
+    for _ in range(3):
+        r = rng.uniform(-1, 1, o.n())
+        np.testing.assert_allclose(o.vcycle_lex(r), bf.vcycle_dense(As, cs, Rs, r), rtol=1e-12, atol=1e-14)
+
+
+def test_lex_vcycle_linear_symmetric_positive():
+    rng = np.random.default_rng(25)
+    o = Oracle(16, 16, 16, levels=4)
+    u, v = rng.uniform(-1, 1, o.n()), rng.uniform(-1, 1, o.n())
+    Mu, Mv = o.vcycle_lex(u), o.vcycle_lex(v)
+    np.testing.assert_allclose(o.vcycle_lex(2.0 * u + 3.0 * v), 2.0 * Mu + 3.0 * Mv, rtol=1e-12, atol=1e-14)
+    a, b = u @ Mv, v @ Mu
+    assert abs(a - b) <= 1e-14 * abs(a)
+    assert u @ Mu > 0 and v @ Mv > 0
+
+
+def test_lex_pcg_krylov_optimal_and_fewer_iterations():
+    rng = np.random.default_rng(26)
+    o = Oracle(4, 4, 4, levels=3)
+    A = o.dense()
+    n = o.n()
+    Minv = np.stack([o.vcycle_lex(e) for e in np.eye(n)], axis=1)
+    b, x0 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    for k in range(1, 5):
+        xk, _, it, st = o.pcg(b, x0=x0, max_iters=k, precond=3)
+        assert it == k and st == 0
+        np.testing.assert_allclose(xk, bf.krylov_optimal(A, Minv, b, x0, k), rtol=1e-9, atol=1e-11)
+    # Sec. III-A: the coloured smoother needs more iterations than the
+    # sequential one it replaces
+    o = Oracle(32, 32, 32, levels=4)
+    b = rng.uniform(0, 1, o.n())
+    _, _, it_lex, st_lex = o.pcg(b, max_iters=100, tol=1e-9, precond=3)
+    _, _, it_col, st_col = o.pcg(b, max_iters=100, tol=1e-9, precond=1)
+    assert st_lex == 0 and st_col == 0 and it_lex < it_col
+
+
 # ----------------------------------------------------------------- PCG (Sec. II-C)
 
 @pytest.mark.parametrize("precond", [0, 1])
