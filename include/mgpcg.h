@@ -58,6 +58,7 @@ typedef enum {
 
 enum { MGPCG_FP64 = 0, MGPCG_FP32 = 1 };
 enum { MGPCG_LAYOUT_NATURAL = 0, MGPCG_LAYOUT_INTERNAL = 1 };
+enum { MGPCG_SMOOTHER_COLOURED = 0, MGPCG_SMOOTHER_SEQUENTIAL = 1 };
 #define MGPCG_MAX_LEVELS 8
 #define MGPCG_MAX_RHS 16
 
@@ -74,6 +75,14 @@ typedef struct {
                             level-0 grid point (packed over grids, natural
                             order); the diagonal becomes 26 + softplus(theta_i)
                             and coarse levels take theta at the injection point */
+    int smoother;        /* MGPCG_SMOOTHER_COLOURED (default): the coloured
+                            symmetric Gauss-Seidel of Sec. III-A;
+                            MGPCG_SMOOTHER_SEQUENTIAL: the sequential symmetric
+                            Gauss-Seidel it replaces (Sec. II-E, Eq. (1): rows
+                            in increasing, then decreasing natural order),
+                            executed wavefront by wavefront
+                            (t = ix + 2 iy + 4 iz).  Requires mg_dtype
+                            MGPCG_FP64 and nrhs 1. */
 } mgpcg_config;
 
 /* Sec. II-A/B, II-D, III-A: build the level hierarchy on the current device:

@@ -47,6 +47,11 @@ int coarse_vcycle_occupancy(int R, bool fp32, int cf, int order);  // resident w
 hipError_t launch_delta_encode(const mgpcg_problem *P, int level, const int64_t *coff_dev, int *flags,
                                hipStream_t s);
 
+// sequential smoother (FP64): wavefront-major copy of a level's values, and
+// one symmetric sweep of Eq. (1) over the level's wavefront schedule
+hipError_t launch_wave_gather(const mgpcg_problem *P, int level, hipStream_t s);
+hipError_t launch_lex_sweep(const mgpcg_problem *P, int level, const double *r, double *z, hipStream_t s);
+
 hipError_t launch_cast_d2f(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_cast_f2d(const float *src, double *dst, int64_t n, hipStream_t s);
 hipError_t launch_fill_d(double *p, int64_t n, double v, hipStream_t s);

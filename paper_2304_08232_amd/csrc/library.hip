@@ -106,6 +106,81 @@ struct Colouring {
 // points of a dimension of extent `ext` whose coordinate has parity `bit`
 inline int64_t half_count(int ext, int bit) { return ext >= 2 ? (ext + 1 - bit) / 2 : (bit ? 0 : 1); }
 
+// Schedule of the sequential smoother on one level (Level::wplan and the
+// wavefront-major tables): every point gets the wavefront number
+// t = ix + 2 iy + 4 iz; a wavefront's rows are kept in internal row order and
+// its positions are padded to a multiple of 64.  The forward plan puts each
+// maximal run of consecutive wavefronts with at most run_rows rows into one
+// single-workgroup launch and gives every larger wavefront a launch of its own.
+mgpcg_status build_waves(mgpcg_problem *P, int l, const std::vector<int32_t> &perm,
+                         const std::vector<int32_t> &iperm, int run_rows, hipStream_t s) {
+    Level &Lv = P->lev[l];
+    int nw = 0;
+    for (const LevelGrid &lg : Lv.grids) nw = std::max(nw, (lg.nx - 1) + 2 * (lg.ny - 1) + 4 * (lg.nz - 1) + 1);
+    auto wave_of = [](int ix, int iy, int iz) { return ix + 2 * iy + 4 * iz; };
+    std::vector<int64_t> cnt(nw, 0);
+    for (const LevelGrid &lg : Lv.grids)
+        for (int iz = 0; iz < lg.nz; ++iz)
+            for (int iy = 0; iy < lg.ny; ++iy)
+                for (int ix = 0; ix < lg.nx; ++ix) ++cnt[wave_of(ix, iy, iz)];
+    std::vector<int64_t> woff(nw + 1, 0);
+    for (int t = 0; t < nw; ++t) woff[t + 1] = woff[t] + (cnt[t] + kEllRows - 1) / kEllRows * kEllRows;
+    const int64_t npos = woff[nw];
+    if (ell_size(npos) >= ((int64_t)1 << 31)) return fail(MGPCG_ERR_DIMS, "problem too large for the sequential smoother");
+    std::vector<int32_t> wrow(npos, -1);
+    std::vector<int64_t> fill(woff.begin(), woff.end() - 1);
+    for (const LevelGrid &lg : Lv.grids)
+        for (int iz = 0; iz < lg.nz; ++iz)
+            for (int iy = 0; iy < lg.ny; ++iy)
+                for (int ix = 0; ix < lg.nx; ++ix) {
+                    const int64_t q = lg.nat_off + ix + (int64_t)lg.nx * (iy + (int64_t)lg.ny * iz);
+                    wrow[fill[wave_of(ix, iy, iz)]++] = perm[q];
+                }
+    for (int t = 0; t < nw; ++t) std::sort(wrow.begin() + woff[t], wrow.begin() + woff[t] + cnt[t]);
+    std::vector<int32_t> wcol(ell_size(npos), 0);
+    std::vector<int64_t> natoff;
+    for (const LevelGrid &lg : Lv.grids) natoff.push_back(lg.nat_off);
+    for (int64_t p = 0; p < npos; ++p) {
+        const int32_t i = wrow[p];
+        if (i < 0) continue;
+        const int64_t q = iperm[i];
+        const int g = (int)(std::upper_bound(natoff.begin(), natoff.end(), q) - natoff.begin()) - 1;
+        const LevelGrid &lg = Lv.grids[g];
+        const int64_t loc = q - lg.nat_off;
+        const int ix = (int)(loc % lg.nx), iy = (int)((loc / lg.nx) % lg.ny), iz = (int)(loc / ((int64_t)lg.nx * lg.ny));
+        for (int sl = 0; sl < kW; ++sl) {
+            const int jx = ix + sl % 3 - 1, jy = iy + (sl / 3) % 3 - 1, jz = iz + sl / 9 - 1;
+            const bool in = jx >= 0 && jx < lg.nx && jy >= 0 && jy < lg.ny && jz >= 0 && jz < lg.nz;
+            wcol[ell_index(sl, p)] = in ? perm[lg.nat_off + jx + (int64_t)lg.nx * (jy + (int64_t)lg.ny * jz)] : i;
+        }
+    }
+    ST_TRY(upload(&Lv.woff_dev, woff, s));
+    ST_TRY(upload(&Lv.wrow, wrow, s));
+    ST_TRY(upload(&Lv.wcol, wcol, s));
+    Lv.nwave = nw;
+    Lv.npos = npos;
+    Lv.woff = woff;
+    Lv.wplan.clear();
+    WaveSeg run{0, 0, true, 0};
+    auto close_run = [&]() {
+        if (run.w1 > run.w0) Lv.wplan.push_back(run);
+        run = WaveSeg{0, 0, true, 0};
+    };
+    for (int t = 0; t < nw; ++t) {
+        const int padded = (int)(woff[t + 1] - woff[t]);
+        if (run_rows > 0 && cnt[t] <= run_rows) {
+            if (run.w1 == run.w0) run.w0 = t;
+            run.w1 = t + 1;
+            run.threads = std::max(run.threads, std::max(padded, kEllRows));
+        } else {
+            close_run();
+            if (cnt[t] > 0) Lv.wplan.push_back(WaveSeg{t, t + 1, false, 0});
+        }
+    }
+    close_run();
+    return MGPCG_OK;
+}
+
 mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t s) {
     const int G = P->G, R = P->R, L = P->L;
     P->lev.resize(L);
@@ -180,6 +255,12 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(upload(&Lv.iperm, iperm, s));
         ST_TRY(upload(&P->d_natoff[l], natoff, s));
         if (l == 0) ST_TRY(upload(&P->d_natoff0, natoff, s));
+        if (P->smoother == MGPCG_SMOOTHER_SEQUENTIAL) {
+            int run_rows = 512;
+            if (const char *env = getenv("MGPCG_LEX_RUN_ROWS"))  // tuning and test override, 0..1024
+                run_rows = std::min(1024, std::max(0, atoi(env)));
+            ST_TRY(build_waves(P, l, perm, iperm, run_rows, s));
+        }
 
         // column bases for the compact column formats, per grid and colour:
         // base[g][k][s] = column - row of the first row of colour k of grid g
@@ -346,6 +427,10 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             Lv.z = z64;
         }
         HIP_TRY(launch_build_ell(P, l, theta, s));
+        if (P->smoother == MGPCG_SMOOTHER_SEQUENTIAL) {
+            ST_TRY(dalloc(&Lv.wval, ell_size(Lv.npos)));
+            HIP_TRY(launch_wave_gather(P, l, s));
+        }
         Lv.cf = 0;
         if (Lv.dbase) {
             // try the compact column formats: implied columns if every delta
@@ -433,7 +518,8 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         // finalize workgroup sums), FP64 V-cycle (whose level-0 z is the CG
         // z), the standard sweep with the double pass (the last update of
         // colour c-1 is that pass)
-        P->fuse_rz = G == 1 && R == 1 && P->mg_dtype == MGPCG_FP64 && L0.ncol == 8;
+        P->fuse_rz = G == 1 && R == 1 && P->mg_dtype == MGPCG_FP64 && L0.ncol == 8 &&
+                     P->smoother == MGPCG_SMOOTHER_COLOURED;
         if (P->fuse_rz) {
             const int rows = pass_block(L0.stream_nt) / R;
             P->rz_off[0] = 0;
@@ -585,6 +671,7 @@ void free_problem(mgpcg_problem *P) {
         dfree(Lv.iperm);
         dfree(Lv.grid_of_nat); dfree(Lv.pass_tab); dfree(Lv.inj_fine); dfree(Lv.inj_coarse);
         dfree(Lv.r); dfree(Lv.z); dfree(Lv.t0); dfree(Lv.t1); dfree(Lv.t2);
+        dfree(Lv.woff_dev); dfree(Lv.wrow); dfree(Lv.wcol); dfree(Lv.wval);
     }
     for (auto &p : P->d_natoff) dfree(p);
     dfree(P->d_dims0); dfree(P->d_natoff0);
@@ -689,9 +776,31 @@ hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, h
     return hipSuccess;
 }
 
+// Listing 1 with the sequential smoother (FP64, one right-hand side): every
+// level starts from z = 0, the restriction and refinement run as their own
+// kernels.
+hipError_t vcycle_lex(const mgpcg_problem *P, const double *r0, double *z0, hipStream_t s) {
+    auto rl = [&](int l) -> double * { return l == 0 ? const_cast<double *>(r0) : (double *)P->lev[l].r; };
+    auto zl = [&](int l) -> double * { return l == 0 ? z0 : (double *)P->lev[l].z; };
+    hipError_t e;
+    for (int l = 0; l < P->L; ++l) {
+        const Level &Lv = P->lev[l];
+        if ((e = launch_fill_d(zl(l), Lv.n, 0.0, s)) != hipSuccess) return e;
+        if ((e = launch_lex_sweep(P, l, rl(l), zl(l), s)) != hipSuccess) return e;
+        if (l + 1 < P->L && (e = launch_restrict<double>(P, l, Lv.val64, rl(l), zl(l), rl(l + 1), s)) != hipSuccess)
+            return e;
+    }
+    for (int l = P->L - 2; l >= 0; --l) {
+        if ((e = launch_prolong<double>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
+        if ((e = launch_lex_sweep(P, l, rl(l), zl(l), s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // z = M^{-1} r on the CG vectors (FP64, internal layout)
 hipError_t precondition(const mgpcg_problem *P, const double *r, double *z, const int *done, hipStream_t s,
                         double *rzp = nullptr) {
+    if (P->smoother == MGPCG_SMOOTHER_SEQUENTIAL) return vcycle_lex(P, r, z, s);
     if (P->mg_dtype == MGPCG_FP64) return vcycle<double>(P, r, z, done, s, rzp);
     const Level &L0 = P->lev[0];
     hipError_t e;
@@ -858,6 +967,10 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
         return fail(MGPCG_ERR_INVALID_ARG, "mg_dtype must be MGPCG_FP64 or MGPCG_FP32");
     if (cfg->colour_order != 0 && cfg->colour_order != 1)
         return fail(MGPCG_ERR_INVALID_ARG, "colour_order must be 0 or 1");
+    if (cfg->smoother != MGPCG_SMOOTHER_COLOURED && cfg->smoother != MGPCG_SMOOTHER_SEQUENTIAL)
+        return fail(MGPCG_ERR_INVALID_ARG, "smoother must be MGPCG_SMOOTHER_COLOURED or MGPCG_SMOOTHER_SEQUENTIAL");
+    if (cfg->smoother == MGPCG_SMOOTHER_SEQUENTIAL && (cfg->mg_dtype != MGPCG_FP64 || R != 1))
+        return fail(MGPCG_ERR_INVALID_ARG, "the sequential smoother needs mg_dtype MGPCG_FP64 and nrhs 1");
     const int div = 1 << (cfg->levels - 1);
     int64_t total = 0;
     for (int g = 0; g < cfg->ngrids; ++g) {
@@ -888,6 +1001,7 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     P->L = cfg->levels;
     P->mg_dtype = cfg->mg_dtype;
     P->colour_order = cfg->colour_order;
+    P->smoother = cfg->smoother;
     P->dims0.assign(cfg->dims, cfg->dims + 3 * cfg->ngrids);
     // tuning and test override: 0 int32 columns, 1 at most int8 deltas, 2 (default) implied columns allowed
     if (const char *env = getenv("MGPCG_DELTA_COLS")) P->col_format = std::min(2, std::max(0, atoi(env)));
@@ -919,7 +1033,10 @@ mgpcg_status mgpcg_info(const mgpcg_problem *p, int level, int64_t *n, int64_t *
 mgpcg_status mgpcg_set_theta(mgpcg_problem *p, const double *theta, hipStream_t stream) {
     ST_TRY(check_problem(p));
     DeviceGuard dg(p->device);
-    for (int l = 0; l < p->L; ++l) HIP_TRY(launch_build_ell(p, l, theta, stream));
+    for (int l = 0; l < p->L; ++l) {
+        HIP_TRY(launch_build_ell(p, l, theta, stream));
+        if (p->smoother == MGPCG_SMOOTHER_SEQUENTIAL) HIP_TRY(launch_wave_gather(p, l, stream));
+    }
     return MGPCG_OK;
 }
 
@@ -996,6 +1113,8 @@ mgpcg_status mgpcg_gs_sweep(const mgpcg_problem *p_, int level, const double *r,
     mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
     DeviceGuard dg(p->device);
     return with_level_vectors(p, level, r, z, layout, s, true, [&](const void *rv, void *zv) {
+        if (p->smoother == MGPCG_SMOOTHER_SEQUENTIAL)
+            return launch_lex_sweep(p, level, (const double *)rv, (double *)zv, s);
         if (p->mg_dtype == MGPCG_FP64)
             return sweep<double>(p, level, p->lev[level].val64, (const double *)rv, (double *)zv, kPassPlain,
                                  kPassPlain, (double *)nullptr, nullptr, s);
@@ -1079,6 +1198,7 @@ mgpcg_status mgpcg_mg_vcycle(const mgpcg_problem *p_, const double *r, double *z
     DeviceGuard dg(p->device);
     ST_TRY(reset_coarse(p, s));
     return with_level_vectors(p, 0, r, z, layout, s, false, [&](const void *rv, void *zv) {
+        if (p->smoother == MGPCG_SMOOTHER_SEQUENTIAL) return vcycle_lex(p, (const double *)rv, (double *)zv, s);
         if (p->mg_dtype == MGPCG_FP64) return vcycle<double>(p, (const double *)rv, (double *)zv, nullptr, s);
         return vcycle<float>(p, (const float *)rv, (float *)zv, nullptr, s);
     });

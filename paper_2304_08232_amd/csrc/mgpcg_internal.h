@@ -65,6 +65,15 @@ struct Seg {
     int16_t colour;
 };
 
+// One launch of the sequential smoother's schedule: wavefronts w0 .. w1-1,
+// either a run of small wavefronts swept by one workgroup of `threads`
+// threads (run), or one wavefront over as many workgroups as it needs.
+struct WaveSeg {
+    int w0, w1;
+    bool run;
+    int threads;
+};
+
 struct LevelGrid {  // one grid at one level
     int nx, ny, nz;
     int ncol;            // colours of this grid (8 unless a dim is 1)
@@ -112,6 +121,20 @@ struct Level {
     int32_t *inj_fine = nullptr;
     int32_t *inj_coarse = nullptr;
     int64_t n_inj = 0;
+
+    // sequential smoother (Eq. (1)) by wavefronts t = ix + 2 iy + 4 iz:
+    // positions woff[t] .. woff[t+1] (multiples of 64) hold the rows of
+    // wavefront t; wrow maps a position to its internal row (-1: padding);
+    // wval / wcol at ell_index(s, position) are the row's values and internal
+    // columns (padding slots: value 0, column = the row itself)
+    int nwave = 0;
+    int64_t npos = 0;
+    std::vector<int64_t> woff;
+    int64_t *woff_dev = nullptr;
+    int32_t *wrow = nullptr;
+    int32_t *wcol = nullptr;
+    double *wval = nullptr;
+    std::vector<WaveSeg> wplan;  // launches of the forward sweep, in order
 
     // V-cycle workspaces in the V-cycle precision (n*R elements)
     void *r = nullptr;
@@ -163,6 +186,7 @@ struct mgpcg_problem {
     int G = 1, R = 1, S = 1, L = 1;
     int mg_dtype = MGPCG_FP64;
     int colour_order = 0;
+    int smoother = MGPCG_SMOOTHER_COLOURED;
     // most compact column format allowed (Level::cf), 2 by default
     int col_format = 2;
     std::vector<int> dims0;  // 3*G, level 0

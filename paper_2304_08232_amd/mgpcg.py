@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmgpcg.so")
 
 FP64, FP32 = 0, 1
 NATURAL, INTERNAL = 0, 1
+SMOOTHER_COLOURED, SMOOTHER_SEQUENTIAL = 0, 1
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID_ARG", -2: "ERR_DIMS", -3: "ERR_OOM",
           -4: "ERR_HIP", -5: "ERR_BREAKDOWN", -6: "ERR_NO_DEVICE"}
 OK, NOT_CONVERGED, ERR_BREAKDOWN = 0, 1, -5
@@ -40,7 +41,7 @@ class MGPCGError(RuntimeError):
 class _Config(C.Structure):
     _fields_ = [("ngrids", C.c_int), ("dims", C.POINTER(C.c_int)), ("levels", C.c_int),
                 ("nrhs", C.c_int), ("mg_dtype", C.c_int), ("colour_order", C.c_int),
-                ("theta", C.c_void_p)]
+                ("theta", C.c_void_p), ("smoother", C.c_int)]
 
 
 _lib = None
@@ -104,12 +105,13 @@ def _ptr(t):
 
 # ------------------------------------------------------- C-ABI-named calls
 
-def mgpcg_create(dims, levels=4, nrhs=1, mg_dtype=FP64, colour_order=0, theta=None, stream=None):
+def mgpcg_create(dims, levels=4, nrhs=1, mg_dtype=FP64, colour_order=0, theta=None, stream=None,
+                 smoother=SMOOTHER_COLOURED):
     """dims: list of (nx, ny, nz).  Returns the opaque handle (int)."""
     flat = [int(d) for g in dims for d in g]
     arr = (C.c_int * len(flat))(*flat)
     cfg = _Config(len(dims), arr, levels, nrhs, mg_dtype, colour_order,
-                  None if theta is None else _ptr(theta).value)
+                  None if theta is None else _ptr(theta).value, smoother)
     h = C.c_void_p()
     _check(lib().mgpcg_create(C.byref(cfg), _stream(stream), C.byref(h)))
     return h.value
@@ -206,7 +208,8 @@ def mgpcg_check(h, stream=None):
 class Problem:
     """A level hierarchy of G grids x R right-hand sides on the current GPU."""
 
-    def __init__(self, dims, levels=4, nrhs=1, mg_dtype="fp64", colour_order=0, theta=None, stream=None):
+    def __init__(self, dims, levels=4, nrhs=1, mg_dtype="fp64", colour_order=0, theta=None, stream=None,
+                 smoother="coloured"):
         if isinstance(dims[0], int):
             dims = [tuple(dims)]
         self.dims = [tuple(int(v) for v in d) for d in dims]
@@ -215,7 +218,9 @@ class Problem:
         self.mg_dtype = mg_dtype
         self.colour_order = colour_order
         dt = {"fp64": FP64, "fp32": FP32}[mg_dtype]
-        self.h = mgpcg_create(self.dims, levels, nrhs, dt, colour_order, theta, stream)
+        self.smoother = smoother
+        sm = {"coloured": SMOOTHER_COLOURED, "sequential": SMOOTHER_SEQUENTIAL}[smoother]
+        self.h = mgpcg_create(self.dims, levels, nrhs, dt, colour_order, theta, stream, sm)
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     def close(self):

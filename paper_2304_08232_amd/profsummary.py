@@ -82,7 +82,7 @@ def kernel_source_hash():
     """Hash of the kernel sources; a stored counter figure is valid only for it."""
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
-    for f in ("kernels.hip", "library.hip", "kernels.h", "mgpcg_internal.h"):
+    for f in ("kernels.hip", "wavefront.hip", "library.hip", "kernels.h", "mgpcg_internal.h"):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
