@@ -12,8 +12,9 @@ Also reported on the same line:
                 events on the stream it runs on, against 8 TB/s;
   cpu_baseline  the CPU oracle (single thread) on a bounded sample;
   extensions    FP32-V-cycle vs FP64 to 1e-9 at 192^3, 64 batched uneven
-                grids and 16 right-hand sides vs one-at-a-time solves, and
-                both colour numberings to 1e-9 at 64^3 and 128^3.
+                grids and 16 right-hand sides vs one-at-a-time solves, both
+                colour numberings to 1e-9 at 64^3 and 128^3, and the
+                sequential (wavefront) smoother against the coloured one.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extensions]
        [--no-cpu-baseline] [--only-kernel]
@@ -208,6 +209,46 @@ def extensions(torch, mg):
         row["time_ratio_order1_vs_order0"] = round(row["order1_s"] / row["order0_s"], 3)
         ext["colour_order"][f"{dims[0]}cubed_uniform_rhs"] = row
         log("colour order:", dims, row)
+
+    # the sequential smoother the coloured one replaces, run wavefront by
+    # wavefront: iterations and time to 1e-9 on the same problems, and the
+    # cost of one V-cycle and of one level-0 sweep of each smoother
+    def event_us(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(e) / reps * 1e3
+
+    ext["sequential_smoother"] = {}
+    for dims, seed in (((64, 64, 64), 7), ((128, 128, 128), 8)):
+        n = dims[0] * dims[1] * dims[2]
+        bo = torch.tensor(inputs.uniform(seed, n), device="cuda")
+        row = {}
+        for name, kw in (("coloured", {}), ("sequential", {"smoother": "sequential"})):
+            po = mg.Problem(dims, levels=LEVELS, **kw)
+            if name == "sequential":
+                to, (xo, ho, ito, sto) = time_to_tol(torch, po, bo, 1e-9, reps=1)
+                row["sequential_iters"] = int(ito[0])
+                row["sequential_s"] = round(to, 4)
+                row["sequential_converged"] = bool(sto == mg.OK)
+            r = po.to_internal(bo)
+            z = torch.zeros_like(r)
+            row[f"{name}_vcycle_us"] = round(event_us(lambda: mg.mgpcg_mg_vcycle(po.h, r, z, mg.INTERNAL), 3), 1)
+            row[f"{name}_l0_sweep_us"] = round(
+                event_us(lambda: mg.mgpcg_gs_sweep(po.h, 0, r, z, mg.INTERNAL), 3), 1)
+            po.close()
+        key = f"{dims[0]}cubed_uniform_rhs"
+        co = ext["colour_order"][key]
+        row["coloured_order0_iters"] = co["order0_iters"]
+        row["coloured_order0_s"] = co["order0_s"]
+        row["time_ratio_sequential_vs_coloured"] = round(row["sequential_s"] / co["order0_s"], 1)
+        ext["sequential_smoother"][key] = row
+        log("sequential smoother:", dims, row)
     return ext
 
 

@@ -256,9 +256,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(upload(&P->d_natoff[l], natoff, s));
         if (l == 0) ST_TRY(upload(&P->d_natoff0, natoff, s));
         if (P->smoother == MGPCG_SMOOTHER_SEQUENTIAL) {
-            int run_rows = 512;
-            if (const char *env = getenv("MGPCG_LEX_RUN_ROWS"))  // tuning and test override, 0..1024
-                run_rows = std::min(1024, std::max(0, atoi(env)));
+            int run_rows = 256;  // the largest wavefront a single-workgroup run takes
+            if (const char *env = getenv("MGPCG_LEX_RUN_ROWS"))  // tuning and test override, 0..512
+                run_rows = std::min(512, std::max(0, atoi(env)));
             ST_TRY(build_waves(P, l, perm, iperm, run_rows, s));
         }
 

@@ -9,7 +9,7 @@ coloured smoother.
 
 MGPCG_LEX_RUN_ROWS sets the largest wavefront a single-workgroup run takes:
 "0" gives every wavefront a launch of its own, "64" mixes both launch kinds,
-"1024" puts whole small levels into single-workgroup runs.
+"512" puts whole small levels into single-workgroup runs.
 """
 import numpy as np
 import pytest
@@ -21,7 +21,7 @@ from parity import assert_history_close
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-RUN_ROWS = ["0", "64", "1024"]
+RUN_ROWS = ["0", "64", "512"]
 
 
 @pytest.fixture(scope="module")
