@@ -198,6 +198,7 @@ ora_hier *ora_create(int nx, int ny, int nz, int levels, int colour_order,
     if (!h) return NULL;
     h->levels = levels;
     h->colour_order = colour_order;
+    h->sweeps = 1;
     double *th = NULL;
     if (theta) {
         int64_t n0 = (int64_t)nx * ny * nz;
@@ -351,11 +352,28 @@ void ora_sgs_lex(const ora_hier *h, int level, const double *r, double *z) {
     for (int64_t i = L->n - 1; i >= 0; --i) gs_row(L, i, r, z);
 }
 
+/*
+ * The smoother of Listing 1 (its lines 2 and 10): h->sweeps symmetric sweeps
+ * in a row (Sec. V notes that several runs may help convergence; one is the
+ * default), coloured or sequential.
+ */
+static void smooth(const ora_hier *h, int level, const double *r, double *z, int lex) {
+    for (int k = 0; k < h->sweeps; ++k) {
+        if (lex) ora_sgs_lex(h, level, r, z); else ora_sgs(h, level, r, z);
+    }
+}
+
+int ora_set_sweeps(ora_hier *h, int sweeps) {
+    if (sweeps < 1) return -1;
+    h->sweeps = sweeps;
+    return 0;
+}
+
 /* Listing 1 with the smoother chosen by `lex` (0: coloured, 1: sequential). */
 static void vcycle_with(const ora_hier *h, int level, const double *r, double *z, int lex) {
     const ora_level *L = &h->lev[level];
     memset(z, 0, (size_t)L->n * sizeof(double));
-    if (lex) ora_sgs_lex(h, level, r, z); else ora_sgs(h, level, r, z);
+    smooth(h, level, r, z, lex);
     if (level == h->levels - 1) return;
     const ora_level *C = &h->lev[level + 1];
     double *rc = (double *)xcalloc((size_t)C->n, sizeof(double));
@@ -363,7 +381,7 @@ static void vcycle_with(const ora_hier *h, int level, const double *r, double *z
     ora_restrict(h, level, r, z, rc);
     vcycle_with(h, level + 1, rc, zc, lex);
     ora_prolong_add(h, level, zc, z);
-    if (lex) ora_sgs_lex(h, level, r, z); else ora_sgs(h, level, r, z);
+    smooth(h, level, r, z, lex);
     free(rc);
     free(zc);
 }
@@ -414,7 +432,7 @@ void ora_sgs32(const ora_hier *h, int level, const float *r, float *z) {
 static void vcycle32_level(const ora_hier *h, int level, const float *r, float *z) {
     const ora_level *L = &h->lev[level];
     memset(z, 0, (size_t)L->n * sizeof(float));
-    ora_sgs32(h, level, r, z);
+    for (int k = 0; k < h->sweeps; ++k) ora_sgs32(h, level, r, z);
     if (level == h->levels - 1) return;
     const ora_level *C = &h->lev[level + 1];
     float *f = (float *)xcalloc((size_t)L->n, sizeof(float));
@@ -424,7 +442,7 @@ static void vcycle32_level(const ora_hier *h, int level, const float *r, float *
     for (int64_t j = 0; j < C->n; ++j) rc[j] = r[L->f2c[j]] - f[L->f2c[j]];
     vcycle32_level(h, level + 1, rc, zc);
     for (int64_t j = 0; j < C->n; ++j) z[L->f2c[j]] += zc[j];
-    ora_sgs32(h, level, r, z);
+    for (int k = 0; k < h->sweeps; ++k) ora_sgs32(h, level, r, z);
     free(f);
     free(rc);
     free(zc);

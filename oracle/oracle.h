@@ -48,6 +48,7 @@ typedef struct {
 typedef struct {
     int levels;
     int colour_order;   /* 0: greedy numbering as found; 1: numbering reversed */
+    int sweeps;         /* symmetric sweeps per smoothing step of the V-cycle (1) */
     ora_level lev[ORA_MAX_LEVELS];
 } ora_hier;
 
@@ -57,6 +58,9 @@ typedef struct {
 ora_hier *ora_create(int nx, int ny, int nz, int levels, int colour_order,
                      const double *theta);
 void ora_destroy(ora_hier *h);
+/* Symmetric sweeps per smoothing step of every V-cycle (default 1); returns
+ * -1 and changes nothing if sweeps < 1. */
+int ora_set_sweeps(ora_hier *h, int sweeps);
 
 /* Introspection (for tests). */
 int64_t ora_n(const ora_hier *h, int level);

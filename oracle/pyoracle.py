@@ -24,6 +24,8 @@ def lib():
         L.ora_create.restype = vp
         L.ora_create.argtypes = [i32, i32, i32, i32, i32, vp]
         L.ora_destroy.argtypes = [vp]
+        L.ora_set_sweeps.restype = i32
+        L.ora_set_sweeps.argtypes = [vp, i32]
         L.ora_n.restype = i64
         L.ora_n.argtypes = [vp, i32]
         L.ora_nnz.restype = i64
@@ -64,7 +66,7 @@ def _f64(a):
 class Oracle:
     """One level hierarchy of the MG-PCG problem, built by the C oracle."""
 
-    def __init__(self, nx, ny, nz, levels=4, colour_order=0, theta=None):
+    def __init__(self, nx, ny, nz, levels=4, colour_order=0, theta=None, sweeps=1):
         self.dims = (nx, ny, nz)
         self.levels = levels
         self.colour_order = colour_order
@@ -75,6 +77,9 @@ class Oracle:
         self._h = lib().ora_create(nx, ny, nz, levels, colour_order, None if th is None else _p(th))
         if not self._h:
             raise ValueError(f"oracle: invalid problem {nx}x{ny}x{nz} levels={levels}")
+        if lib().ora_set_sweeps(self._h, sweeps) != 0:
+            self.close()
+            raise ValueError(f"oracle: invalid sweep count {sweeps}")
 
     def close(self):
         if self._h:

@@ -70,17 +70,21 @@ def injection_matrix(nx, ny, nz):
     return R
 
 
-def vcycle_dense(levels_A, levels_colour, levels_R, r, l=0):
-    """Brute-force V-cycle from dense pieces."""
+def vcycle_dense(levels_A, levels_colour, levels_R, r, l=0, nu=1):
+    """Brute-force V-cycle from dense pieces; nu symmetric sweeps per smoothing."""
     A = levels_A[l]
-    z = sgs_sequential(A, r, np.zeros_like(r), levels_colour[l])
+    z = np.zeros_like(r)
+    for _ in range(nu):
+        z = sgs_sequential(A, r, z, levels_colour[l])
     if l == len(levels_A) - 1:
         return z
     R = levels_R[l]
     rc = R @ (r - A @ z)
-    zc = vcycle_dense(levels_A, levels_colour, levels_R, rc, l + 1)
+    zc = vcycle_dense(levels_A, levels_colour, levels_R, rc, l + 1, nu)
     z = z + R.T @ zc
-    return sgs_sequential(A, r, z, levels_colour[l])
+    for _ in range(nu):
+        z = sgs_sequential(A, r, z, levels_colour[l])
+    return z
 
 
 def krylov_optimal(A, Minv, b, x0, k):

@@ -339,6 +339,68 @@ def test_lex_pcg_krylov_optimal_and_fewer_iterations():
     assert st_lex == 0 and st_col == 0 and it_lex < it_col
 
 
+# ------------------------------------ several smoother sweeps (Listing 1, Sec. V)
+
+@pytest.mark.parametrize("nu", [2, 3])
+@pytest.mark.parametrize("order,lex", [(0, False), (1, False), (0, True)])
+def test_sweeps_vcycle_equals_dense_bruteforce(nu, order, lex):
+    rng = np.random.default_rng(27)
+    o = Oracle(8, 8, 4, levels=3, colour_order=order, sweeps=nu)
+    As, cs, Rs = _dense_hierarchy(o)
+    if lex:
+        cs = [np.zeros(o.n(l), dtype=np.int64) for l in range(o.levels)]
+    r = rng.uniform(-1, 1, o.n())
+    got = o.vcycle_lex(r) if lex else o.vcycle(r)
+    np.testing.assert_allclose(got, bf.vcycle_dense(As, cs, Rs, r, nu=nu), rtol=1e-12, atol=1e-14)
+
+
+def test_sweeps_one_level_is_the_truncated_neumann_series():
+    # one level: nu sweeps from z = 0 give sum_{k<nu} (I - B A)^k B r, with B
+    # the one-sweep operator (its columns are sweeps of unit vectors)
+    rng = np.random.default_rng(28)
+    o1 = Oracle(6, 5, 4, levels=1)
+    A = o1.dense()
+    n = o1.n()
+    B = np.stack([o1.vcycle(e) for e in np.eye(n)], axis=1)
+    r = rng.uniform(-1, 1, n)
+    E = np.eye(n) - B @ A
+    for nu in (2, 4):
+        ref = sum(np.linalg.matrix_power(E, k) @ B @ r for k in range(nu))
+        np.testing.assert_allclose(Oracle(6, 5, 4, levels=1, sweeps=nu).vcycle(r), ref, rtol=1e-11, atol=1e-13)
+    # many sweeps converge to the solution
+    np.testing.assert_allclose(Oracle(6, 5, 4, levels=1, sweeps=60).vcycle(r), np.linalg.solve(A, r),
+                               rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("lex", [False, True])
+def test_sweeps_vcycle_symmetric_and_fewer_iterations(lex):
+    rng = np.random.default_rng(29)
+    o = Oracle(16, 16, 16, levels=4, sweeps=2)
+    vc = o.vcycle_lex if lex else o.vcycle
+    u, v = rng.uniform(-1, 1, o.n()), rng.uniform(-1, 1, o.n())
+    a, b = u @ vc(v), v @ vc(u)
+    assert abs(a - b) <= 1e-14 * abs(a) and u @ vc(u) > 0
+    # Sec. V: several smoother runs may improve convergence
+    b = rng.uniform(0, 1, 32 ** 3)
+    its = []
+    for nu in (1, 2, 3):
+        _, _, it, st = Oracle(32, 32, 32, levels=4, sweeps=nu).pcg(b, max_iters=100, tol=1e-9,
+                                                                    precond=3 if lex else 1)
+        assert st == 0
+        its.append(it)
+    assert its[0] > its[1] >= its[2]
+
+
+def test_sweeps_fp32_close_to_fp64_and_invalid():
+    rng = np.random.default_rng(30)
+    o = Oracle(16, 16, 16, levels=4, sweeps=2)
+    r = rng.uniform(-1, 1, o.n())
+    z64 = o.vcycle(r)
+    assert np.linalg.norm(o.vcycle32(r) - z64) <= 1e-5 * np.linalg.norm(z64)
+    with pytest.raises(ValueError):
+        Oracle(4, 4, 4, levels=2, sweeps=0)
+
+
 # ----------------------------------------------------------------- PCG (Sec. II-C)
 
 @pytest.mark.parametrize("precond", [0, 1])
