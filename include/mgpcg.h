@@ -61,6 +61,7 @@ enum { MGPCG_LAYOUT_NATURAL = 0, MGPCG_LAYOUT_INTERNAL = 1 };
 enum { MGPCG_SMOOTHER_COLOURED = 0, MGPCG_SMOOTHER_SEQUENTIAL = 1 };
 #define MGPCG_MAX_LEVELS 8
 #define MGPCG_MAX_RHS 16
+#define MGPCG_MAX_SWEEPS 16
 
 typedef struct {
     int ngrids;          /* G >= 1 */
@@ -83,6 +84,10 @@ typedef struct {
                             executed wavefront by wavefront
                             (t = ix + 2 iy + 4 iz).  Requires mg_dtype
                             MGPCG_FP64 and nrhs 1. */
+    int sweeps;          /* symmetric sweeps per smoothing step of the V-cycle
+                            (Listing 1, lines 2 and 10, and the coarsest
+                            level), 0..MGPCG_MAX_SWEEPS; 0 means 1, the
+                            default of the paper's experiments (Sec. V). */
 } mgpcg_config;
 
 /* Sec. II-A/B, II-D, III-A: build the level hierarchy on the current device:
@@ -201,10 +206,10 @@ mgpcg_status mgpcg_set_graph_mode(mgpcg_problem *p, int on);
 /* Execution of the coarse levels of the V-cycle: mode 0 (default) launches
  * one kernel per colour pass; mode 1 runs levels 1..L-1 of each V-cycle in
  * one persistent launch whose workgroups separate the phases with a grid
- * barrier (used when nrhs is 1, every coarse grid has the standard 8-colour
- * numbering and the coarse levels share one column format, int32 when the
- * problem has several grids; otherwise mode 0 runs).  Results are identical
- * either way. */
+ * barrier (used when nrhs is 1, sweeps is 1, the smoother is the coloured
+ * one, every coarse grid has the standard 8-colour numbering and the coarse
+ * levels share one column format, int32 when the problem has several grids;
+ * otherwise mode 0 runs).  Results are identical either way. */
 mgpcg_status mgpcg_set_coarse_mode(mgpcg_problem *p, int mode);
 
 /* Synchronises the stream and reports a device-side failure of earlier

@@ -556,7 +556,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
     {
         const bool fp32 = P->mg_dtype == MGPCG_FP32;
         auto eligible = [&](int from) {
-            bool ok = from >= 1 && from < L && R == 1;
+            bool ok = from >= 1 && from < L && R == 1 && P->sweeps == 1;
             for (int l = from; l < L && ok; ++l) ok = P->lev[l].zs_std && P->lev[l].ncol == 8;
             const int cf = ok ? P->lev[from].cf : 0;
             for (int l = from; l < L && ok; ++l) ok = P->lev[l].cf == cf;
@@ -649,7 +649,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         const int64_t need = Lt.n * 2 * (fp32 ? 4 : 8);
         bool fits = true;
         for (int k = 0; k < Lt.ncol; ++k) fits = fits && Lt.coff[k + 1] - Lt.coff[k] <= kTailBlock;
-        P->tail_ok = L >= 2 && R == 1 && Lt.zs_std && Lt.ncol == 8 && need <= tail_bytes &&
+        P->tail_ok = L >= 2 && R == 1 && P->sweeps == 1 && Lt.zs_std && Lt.ncol == 8 && need <= tail_bytes &&
                      need <= (64 << 10) && fits && (G == 1 || Lt.cf == 0);
         P->tail_lw = P->tail_ok ? L - 1 : L;
     }
@@ -756,10 +756,13 @@ hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, h
         }
         const bool coarser = l + 1 < P->L;
         const bool fuse = coarser && Lv.fuse_transfers;
-        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), zs ? kPassZeroStart : kPassPlain,
-                          fuse ? kPassRestrict : kPassPlain, coarser ? rl(l + 1) : nullptr, done, s)) !=
-            hipSuccess)
-            return e;
+        // pre-smoothing: P->sweeps symmetric sweeps; the first may start from
+        // zero, the last may carry the restriction
+        for (int k = 0; k < P->sweeps; ++k)
+            if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), zs && k == 0 ? kPassZeroStart : kPassPlain,
+                              fuse && k == P->sweeps - 1 ? kPassRestrict : kPassPlain,
+                              coarser ? rl(l + 1) : nullptr, done, s)) != hipSuccess)
+                return e;
         if (coarser && !fuse &&
             (e = launch_restrict<T>(P, l, level_val<T>(P, l), rl(l), zl(l), rl(l + 1), s)) != hipSuccess)
             return e;
@@ -769,16 +772,20 @@ hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, h
     for (int l = (persistent || tail ? L - 1 : L - 2); l >= 0; --l) {
         const bool fuse = P->lev[l].fuse_transfers;
         if (!fuse && (e = launch_prolong<T>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
-        if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), fuse ? kPassProlong : kPassPlain, kPassPlain,
-                          zl(l + 1), done, s, l == 0 ? rzp : nullptr)) != hipSuccess)
-            return e;
+        // post-smoothing: the first sweep may carry the refinement, the last
+        // writes the <r,z> partials
+        for (int k = 0; k < P->sweeps; ++k)
+            if ((e = sweep<T>(P, l, level_val<T>(P, l), rl(l), zl(l), fuse && k == 0 ? kPassProlong : kPassPlain,
+                              kPassPlain, zl(l + 1), done, s,
+                              l == 0 && k == P->sweeps - 1 ? rzp : nullptr)) != hipSuccess)
+                return e;
     }
     return hipSuccess;
 }
 
 // Listing 1 with the sequential smoother (FP64, one right-hand side): every
-// level starts from z = 0, the restriction and refinement run as their own
-// kernels.
+// level starts from z = 0, each smoothing step is P->sweeps symmetric sweeps,
+// the restriction and refinement run as their own kernels.
 hipError_t vcycle_lex(const mgpcg_problem *P, const double *r0, double *z0, hipStream_t s) {
     auto rl = [&](int l) -> double * { return l == 0 ? const_cast<double *>(r0) : (double *)P->lev[l].r; };
     auto zl = [&](int l) -> double * { return l == 0 ? z0 : (double *)P->lev[l].z; };
@@ -786,13 +793,15 @@ hipError_t vcycle_lex(const mgpcg_problem *P, const double *r0, double *z0, hipS
     for (int l = 0; l < P->L; ++l) {
         const Level &Lv = P->lev[l];
         if ((e = launch_fill_d(zl(l), Lv.n, 0.0, s)) != hipSuccess) return e;
-        if ((e = launch_lex_sweep(P, l, rl(l), zl(l), s)) != hipSuccess) return e;
+        for (int k = 0; k < P->sweeps; ++k)
+            if ((e = launch_lex_sweep(P, l, rl(l), zl(l), s)) != hipSuccess) return e;
         if (l + 1 < P->L && (e = launch_restrict<double>(P, l, Lv.val64, rl(l), zl(l), rl(l + 1), s)) != hipSuccess)
             return e;
     }
     for (int l = P->L - 2; l >= 0; --l) {
         if ((e = launch_prolong<double>(P, l, zl(l + 1), zl(l), s)) != hipSuccess) return e;
-        if ((e = launch_lex_sweep(P, l, rl(l), zl(l), s)) != hipSuccess) return e;
+        for (int k = 0; k < P->sweeps; ++k)
+            if ((e = launch_lex_sweep(P, l, rl(l), zl(l), s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -969,6 +978,8 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
         return fail(MGPCG_ERR_INVALID_ARG, "colour_order must be 0 or 1");
     if (cfg->smoother != MGPCG_SMOOTHER_COLOURED && cfg->smoother != MGPCG_SMOOTHER_SEQUENTIAL)
         return fail(MGPCG_ERR_INVALID_ARG, "smoother must be MGPCG_SMOOTHER_COLOURED or MGPCG_SMOOTHER_SEQUENTIAL");
+    if (cfg->sweeps < 0 || cfg->sweeps > MGPCG_MAX_SWEEPS)
+        return fail(MGPCG_ERR_INVALID_ARG, "sweeps must be in 0.." + std::to_string(MGPCG_MAX_SWEEPS));
     if (cfg->smoother == MGPCG_SMOOTHER_SEQUENTIAL && (cfg->mg_dtype != MGPCG_FP64 || R != 1))
         return fail(MGPCG_ERR_INVALID_ARG, "the sequential smoother needs mg_dtype MGPCG_FP64 and nrhs 1");
     const int div = 1 << (cfg->levels - 1);
@@ -1002,6 +1013,7 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     P->mg_dtype = cfg->mg_dtype;
     P->colour_order = cfg->colour_order;
     P->smoother = cfg->smoother;
+    P->sweeps = cfg->sweeps == 0 ? 1 : cfg->sweeps;
     P->dims0.assign(cfg->dims, cfg->dims + 3 * cfg->ngrids);
     // tuning and test override: 0 int32 columns, 1 at most int8 deltas, 2 (default) implied columns allowed
     if (const char *env = getenv("MGPCG_DELTA_COLS")) P->col_format = std::min(2, std::max(0, atoi(env)));

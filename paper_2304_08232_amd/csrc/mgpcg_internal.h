@@ -187,6 +187,7 @@ struct mgpcg_problem {
     int mg_dtype = MGPCG_FP64;
     int colour_order = 0;
     int smoother = MGPCG_SMOOTHER_COLOURED;
+    int sweeps = 1;  // symmetric sweeps per smoothing step of the V-cycle
     // most compact column format allowed (Level::cf), 2 by default
     int col_format = 2;
     std::vector<int> dims0;  // 3*G, level 0

@@ -41,7 +41,7 @@ class MGPCGError(RuntimeError):
 class _Config(C.Structure):
     _fields_ = [("ngrids", C.c_int), ("dims", C.POINTER(C.c_int)), ("levels", C.c_int),
                 ("nrhs", C.c_int), ("mg_dtype", C.c_int), ("colour_order", C.c_int),
-                ("theta", C.c_void_p), ("smoother", C.c_int)]
+                ("theta", C.c_void_p), ("smoother", C.c_int), ("sweeps", C.c_int)]
 
 
 _lib = None
@@ -106,12 +106,12 @@ def _ptr(t):
 # ------------------------------------------------------- C-ABI-named calls
 
 def mgpcg_create(dims, levels=4, nrhs=1, mg_dtype=FP64, colour_order=0, theta=None, stream=None,
-                 smoother=SMOOTHER_COLOURED):
+                 smoother=SMOOTHER_COLOURED, sweeps=1):
     """dims: list of (nx, ny, nz).  Returns the opaque handle (int)."""
     flat = [int(d) for g in dims for d in g]
     arr = (C.c_int * len(flat))(*flat)
     cfg = _Config(len(dims), arr, levels, nrhs, mg_dtype, colour_order,
-                  None if theta is None else _ptr(theta).value, smoother)
+                  None if theta is None else _ptr(theta).value, smoother, sweeps)
     h = C.c_void_p()
     _check(lib().mgpcg_create(C.byref(cfg), _stream(stream), C.byref(h)))
     return h.value
@@ -209,7 +209,7 @@ class Problem:
     """A level hierarchy of G grids x R right-hand sides on the current GPU."""
 
     def __init__(self, dims, levels=4, nrhs=1, mg_dtype="fp64", colour_order=0, theta=None, stream=None,
-                 smoother="coloured"):
+                 smoother="coloured", sweeps=1):
         if isinstance(dims[0], int):
             dims = [tuple(dims)]
         self.dims = [tuple(int(v) for v in d) for d in dims]
@@ -220,7 +220,8 @@ class Problem:
         dt = {"fp64": FP64, "fp32": FP32}[mg_dtype]
         self.smoother = smoother
         sm = {"coloured": SMOOTHER_COLOURED, "sequential": SMOOTHER_SEQUENTIAL}[smoother]
-        self.h = mgpcg_create(self.dims, levels, nrhs, dt, colour_order, theta, stream, sm)
+        self.sweeps = sweeps
+        self.h = mgpcg_create(self.dims, levels, nrhs, dt, colour_order, theta, stream, sm, sweeps)
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     def close(self):

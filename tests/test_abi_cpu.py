@@ -30,10 +30,10 @@ def test_every_declared_symbol_is_exported():
     assert sorted(mgpcg.ABI_FUNCTIONS) == decl
 
 
-def _cfg(dims, levels=4, nrhs=1, dtype=0, order=0, smoother=0):
+def _cfg(dims, levels=4, nrhs=1, dtype=0, order=0, smoother=0, sweeps=0):
     flat = [v for d in dims for v in d]
     arr = (C.c_int * len(flat))(*flat)
-    cfg = mgpcg._Config(len(dims), arr, levels, nrhs, dtype, order, None, smoother)
+    cfg = mgpcg._Config(len(dims), arr, levels, nrhs, dtype, order, None, smoother, sweeps)
     cfg._keep = arr
     return cfg
 
@@ -53,6 +53,9 @@ def test_argument_errors_without_device():
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], dtype=1, smoother=1)), None, C.byref(h)) == -1
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], nrhs=2, smoother=1)), None, C.byref(h)) == -1
     assert b"sequential smoother" in L.mgpcg_last_error()
+    assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], sweeps=-1)), None, C.byref(h)) == -1
+    assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], sweeps=17)), None, C.byref(h)) == -1
+    assert b"sweeps" in L.mgpcg_last_error()
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], dtype=2)), None, C.byref(h)) == -1
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], order=2)), None, C.byref(h)) == -1
     assert h.value is None
