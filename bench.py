@@ -13,8 +13,11 @@ Also reported on the same line:
   cpu_baseline  the CPU oracle (single thread) on a bounded sample;
   extensions    FP32-V-cycle vs FP64 to 1e-9 at 192^3, 64 batched uneven
                 grids and 16 right-hand sides vs one-at-a-time solves, both
-                colour numberings to 1e-9 at 64^3 and 128^3, and the
-                sequential (wavefront) smoother against the coloured one.
+                colour numberings to 1e-9 at 64^3 and 128^3, the
+                sequential (wavefront) smoother against the coloured one,
+                1-3 sweeps per smoothing step, and an HPCG-style validation
+                (symmetry departures, iterations to match 50 sequential-
+                smoother iterations, timed fixed-iteration sets).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extensions]
        [--no-cpu-baseline] [--only-kernel]
@@ -249,7 +252,95 @@ def extensions(torch, mg):
         row["time_ratio_sequential_vs_coloured"] = round(row["sequential_s"] / co["order0_s"], 1)
         ext["sequential_smoother"][key] = row
         log("sequential smoother:", dims, row)
+
+    # several symmetric sweeps per smoothing step (one is the default)
+    ext["smoother_sweeps"] = {}
+    for dims, seed, cfgs in (((128, 128, 128), 8, (("coloured_order0", {"colour_order": 0}),
+                                                     ("coloured_order1", {"colour_order": 1}))),
+                             ((64, 64, 64), 7, (("sequential", {"smoother": "sequential"}),))):
+        n = dims[0] * dims[1] * dims[2]
+        bo = torch.tensor(inputs.uniform(seed, n), device="cuda")
+        for name, kw in cfgs:
+            row = {}
+            for nu in (1, 2, 3):
+                if name == "sequential" and nu == 3:
+                    continue
+                po = mg.Problem(dims, levels=LEVELS, sweeps=nu, **kw)
+                to, (xo, ho, ito, sto) = time_to_tol(torch, po, bo, 1e-9, reps=1 if name == "sequential" else 3)
+                po.close()
+                row[f"sweeps{nu}_iters"] = int(ito[0])
+                row[f"sweeps{nu}_s"] = round(to, 5)
+                row[f"sweeps{nu}_converged"] = bool(sto == mg.OK)
+            ext["smoother_sweeps"][f"{dims[0]}cubed_{name}"] = row
+            log("smoother sweeps:", dims, name, row)
+
+    ext["hpcg_validation"] = hpcg_validation(torch, mg, inputs)
     return ext
+
+
+def hpcg_validation(torch, mg, inputs, dims=(128, 128, 128), ref_iters=50, sets=10):
+    """HPCG-style acceptance of the coloured smoother against the sequential
+    one it replaces (Sec. III-A), at the benchmark's problem (b = A*1, x0 = 0):
+      symmetry  departure of A and of each preconditioner from symmetry,
+                |x'(Ay) - y'(Ax)| / ((|x| |Ay| + |y| |Ax|) eps), the same for
+                the V-cycle M, with x, y ~ U[-1,1] (seeds 91, 92);
+      iterations  the iterations each configuration needs to reach the
+                relative residual of ref_iters iterations with the sequential
+                smoother;
+      sets      `sets` timed solves of exactly that many iterations;
+      rate      the reference work (ref_iters iterations of the nominal model)
+                divided by the mean time of one set, i.e. the rate after the
+                iteration-count penalty."""
+    from paper_2304_08232_amd import perfmodel
+    _, flops_it = perfmodel.iteration([dims], LEVELS, "fp64")
+    n = dims[0] * dims[1] * dims[2]
+    eps = float(np.finfo(np.float64).eps)
+    xs = torch.tensor(inputs.uniform(91, n), device="cuda")
+    ys = torch.tensor(inputs.uniform(92, n), device="cuda")
+
+    def departure(op):
+        ax, ay = op(xs), op(ys)
+        torch.cuda.synchronize()
+        x, y, ax, ay = (t.cpu().numpy() for t in (xs, ys, ax, ay))
+        num = abs(float(np.dot(x, ay)) - float(np.dot(y, ax)))
+        return float(num / ((np.linalg.norm(x) * np.linalg.norm(ay) + np.linalg.norm(y) * np.linalg.norm(ax)) * eps))
+
+    out = {"reference": "sequential smoother, %d iterations" % ref_iters, "configs": {}}
+    pr = mg.Problem(dims, levels=LEVELS, smoother="sequential")
+    b = pr.make_rhs_ones()
+    x, h, its, st = pr.solve(b, max_iters=ref_iters)
+    target = float(h[0, ref_iters - 1])
+    out["reference_relres"] = target
+    out["symmetry_A"] = round(departure(pr.spmv), 3)
+    out["configs"]["sequential"] = {"symmetry_M": round(departure(pr.vcycle), 3), "iters": ref_iters}
+    pr.close()
+    for name, kw in (("coloured_order0", {}), ("coloured_order1", {"colour_order": 1}),
+                     ("coloured_order0_sweeps2", {"sweeps": 2})):
+        p = mg.Problem(dims, levels=LEVELS, **kw)
+        row = {"symmetry_M": round(departure(p.vcycle), 3)}
+        _, h, its, st = p.solve(b, max_iters=10 * ref_iters, tol=target)
+        k = int(its[0])
+        row["iters"] = k
+        row["reached"] = bool(st == mg.OK)
+        bi = p.to_internal(b)
+        xi = torch.zeros_like(bi)
+        times = []
+        for rep in range(sets + 1):  # the first is a warmup (graph capture)
+            xi.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.solve_async(bi, xi, max_iters=k, layout=mg.INTERNAL)
+            torch.cuda.synchronize()
+            if rep:
+                times.append(time.perf_counter() - t0)
+        p.close()
+        row["set_ms_mean"] = round(1e3 * float(np.mean(times)), 3)
+        row["set_ms_std"] = round(1e3 * float(np.std(times, ddof=1)), 3)
+        row["penalty"] = round(k / ref_iters, 3)
+        row["rate_gflops"] = round(ref_iters * flops_it / float(np.mean(times)) / 1e9, 1)
+        out["configs"][name] = row
+    log("hpcg validation:", out)
+    return out
 
 
 def main():

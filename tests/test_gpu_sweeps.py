@@ -121,3 +121,24 @@ def test_rejected_counts(mg):
     for bad in (-1, 17):
         with pytest.raises(mg.MGPCGError):
             mg.Problem((16, 16, 16), sweeps=bad)
+
+
+def _departure(op, x, y):
+    """|x'(Oy) - y'(Ox)| / ((|x||Oy| + |y||Ox|) eps), the HPCG-style symmetry
+    measure: a few units for an operator symmetric up to rounding."""
+    ox, oy = host(op(dev(x))), host(op(dev(y)))
+    num = abs(float(np.dot(x, oy)) - float(np.dot(y, ox)))
+    return num / ((np.linalg.norm(x) * np.linalg.norm(oy) + np.linalg.norm(y) * np.linalg.norm(ox))
+                  * np.finfo(np.float64).eps)
+
+
+@pytest.mark.parametrize("kw", [{}, {"colour_order": 1}, {"sweeps": 2}, {"smoother": "sequential"},
+                                {"smoother": "sequential", "sweeps": 2}])
+def test_symmetry_departures(mg, kw):
+    # a replacement smoother must keep the preconditioner symmetric
+    # (Sec. III-A); a forward-only coloured smoother shows ~3e12 here
+    dims = (32, 32, 32)
+    x, y = inputs.uniform(91, 32 ** 3), inputs.uniform(92, 32 ** 3)
+    p = mg.Problem(dims, **kw)
+    assert _departure(p.spmv, x, y) < 10
+    assert _departure(p.vcycle, x, y) < 10
