@@ -212,6 +212,56 @@ mgpcg_status mgpcg_set_graph_mode(mgpcg_problem *p, int on);
  * otherwise mode 0 runs).  Results are identical either way. */
 mgpcg_status mgpcg_set_coarse_mode(mgpcg_problem *p, int mode);
 
+/* Execution schedule of a problem: how its kernels are launched, never what
+ * they compute.  A solve gives bit-identical results under every schedule,
+ * except that changing bit 0 of wide_levels on a problem that fuses <r,z>
+ * into the level-0 post-smoother (one grid, one right-hand side, FP64
+ * V-cycle, coloured smoother) regroups that sum's partials, which moves its
+ * rounding. */
+typedef struct {
+    int graph;         /* as mgpcg_set_graph_mode: 1 replay a captured
+                          iteration, 0 launch its kernels one by one */
+    int coarse_mode;   /* as mgpcg_set_coarse_mode */
+    int coarse_tail;   /* 1: the coarsest level of the coloured V-cycle runs in
+                          one single-workgroup kernel when it fits (nrhs 1,
+                          sweeps 1, r and z of the level within 64 KiB, at
+                          most 512 rows per colour); 0: one kernel per pass */
+    unsigned wide_levels; /* bit l: level l's colour passes use 256-thread
+                          workgroups and stream the operator with
+                          non-temporal loads; clear: 64-thread workgroups and
+                          cached loads.  Bits at and above `levels` must be
+                          0.  Default: set for levels whose operator exceeds
+                          128 MiB */
+    int lex_run_rows;  /* sequential smoother: the largest wavefront, in
+                          rows, that a single-workgroup run sweeps (0..512;
+                          0: one launch per wavefront); default 256 */
+} mgpcg_schedule;
+
+/* Reads the current schedule into *out (HOST). */
+mgpcg_status mgpcg_get_schedule(const mgpcg_problem *p, mgpcg_schedule *out);
+
+/* Applies *sched (HOST).  Invalid fields return MGPCG_ERR_INVALID_ARG and
+ * change nothing.  Discards the captured iteration graph; may synchronise the
+ * stream. */
+mgpcg_status mgpcg_set_schedule(mgpcg_problem *p, const mgpcg_schedule *sched, hipStream_t stream);
+
+/* Autotuner for the schedule of this problem.  Times candidate schedules by
+ * coordinate descent from the current one (graph mode; coarse mode and tail;
+ * each level's workgroup choice, leaving bit 0 alone where changing it would
+ * move rounding; the sequential smoother's run limit), each as `reps` timed
+ * runs of `iters` PCG iterations from x = 0 after one warm-up run, keeps the
+ * fastest (best of its runs) and applies it.  b: DEVICE right-hand side in
+ * natural layout, or NULL for b = A*1.  cache_path (HOST string, may be
+ * NULL): a text file with one JSON object per line; if it holds an entry for
+ * this problem (grids, levels, right-hand sides, precision, colour order,
+ * smoother, sweeps) on this kind of device, that schedule is applied without
+ * timing, otherwise the chosen one is appended.  *chosen (HOST, may be NULL)
+ * receives the applied schedule.  iters in 1..1000, reps in 1..100.
+ * Allocates two vectors of the level-0 size for the duration of the call and
+ * synchronises the stream. */
+mgpcg_status mgpcg_autotune(mgpcg_problem *p, const double *b, int iters, int reps, const char *cache_path,
+                            mgpcg_schedule *chosen, hipStream_t stream);
+
 /* Synchronises the stream and reports a device-side failure of earlier
  * asynchronous work on this problem (MGPCG_ERR_HIP, e.g. a coarse-level grid
  * barrier that timed out), else MGPCG_OK. */

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <fstream>
 #include <new>
 #include <string>
 #include <utility>
@@ -106,14 +107,54 @@ struct Colouring {
 // points of a dimension of extent `ext` whose coordinate has parity `bit`
 inline int64_t half_count(int ext, int bit) { return ext >= 2 ? (ext + 1 - bit) / 2 : (bit ? 0 : 1); }
 
-// Schedule of the sequential smoother on one level (Level::wplan and the
-// wavefront-major tables): every point gets the wavefront number
+// <r,z> partials of the level-0 post-smoother: one per workgroup of the last
+// update of each colour; colour k's first at off[k] (off[8]: the count)
+void rz_layout(const mgpcg_problem *P, bool wide, int64_t *off) {
+    const Level &L0 = P->lev[0];
+    const int rows = pass_block(wide) / P->R;
+    off[0] = 0;
+    for (int k = 0; k < 8; ++k) off[k + 1] = off[k] + (L0.coff[k + 1] - L0.coff[k] + rows - 1) / rows;
+}
+
+// rz_off and the finalize table red_gb[2] for the current level-0 workgroup size
+hipError_t set_rz_layout(mgpcg_problem *P, hipStream_t s) {
+    rz_layout(P, P->lev[0].stream_nt, P->rz_off);
+    const int gb[2] = {0, (int)P->rz_off[8]};
+    hipError_t e = hipMemcpyAsync(P->red_gb[2], gb, sizeof(gb), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);  // gb lives on this stack frame
+}
+
+// Forward launch plan of the sequential smoother on one level: each maximal
+// run of consecutive wavefronts with at most run_rows rows goes to one
+// single-workgroup launch, every larger wavefront gets a launch of its own.
+void make_wave_plan(Level &Lv, int run_rows) {
+    Lv.wplan.clear();
+    WaveSeg run{0, 0, true, 0};
+    auto close_run = [&]() {
+        if (run.w1 > run.w0) Lv.wplan.push_back(run);
+        run = WaveSeg{0, 0, true, 0};
+    };
+    for (int t = 0; t < Lv.nwave; ++t) {
+        const int padded = (int)(Lv.woff[t + 1] - Lv.woff[t]);
+        if (run_rows > 0 && Lv.wcnt[t] <= run_rows) {
+            if (run.w1 == run.w0) run.w0 = t;
+            run.w1 = t + 1;
+            run.threads = std::max(run.threads, std::max(padded, kEllRows));
+        } else {
+            close_run();
+            if (Lv.wcnt[t] > 0) Lv.wplan.push_back(WaveSeg{t, t + 1, false, 0});
+        }
+    }
+    close_run();
+}
+
+// Tables of the sequential smoother on one level (the wavefront-major copy
+// but for its values): every point gets the wavefront number
 // t = ix + 2 iy + 4 iz; a wavefront's rows are kept in internal row order and
-// its positions are padded to a multiple of 64.  The forward plan puts each
-// maximal run of consecutive wavefronts with at most run_rows rows into one
-// single-workgroup launch and gives every larger wavefront a launch of its own.
+// its positions are padded to a multiple of 64.
 mgpcg_status build_waves(mgpcg_problem *P, int l, const std::vector<int32_t> &perm,
-                         const std::vector<int32_t> &iperm, int run_rows, hipStream_t s) {
+                         const std::vector<int32_t> &iperm, hipStream_t s) {
     Level &Lv = P->lev[l];
     int nw = 0;
     for (const LevelGrid &lg : Lv.grids) nw = std::max(nw, (lg.nx - 1) + 2 * (lg.ny - 1) + 4 * (lg.nz - 1) + 1);
@@ -160,24 +201,8 @@ mgpcg_status build_waves(mgpcg_problem *P, int l, const std::vector<int32_t> &pe
     Lv.nwave = nw;
     Lv.npos = npos;
     Lv.woff = woff;
-    Lv.wplan.clear();
-    WaveSeg run{0, 0, true, 0};
-    auto close_run = [&]() {
-        if (run.w1 > run.w0) Lv.wplan.push_back(run);
-        run = WaveSeg{0, 0, true, 0};
-    };
-    for (int t = 0; t < nw; ++t) {
-        const int padded = (int)(woff[t + 1] - woff[t]);
-        if (run_rows > 0 && cnt[t] <= run_rows) {
-            if (run.w1 == run.w0) run.w0 = t;
-            run.w1 = t + 1;
-            run.threads = std::max(run.threads, std::max(padded, kEllRows));
-        } else {
-            close_run();
-            if (cnt[t] > 0) Lv.wplan.push_back(WaveSeg{t, t + 1, false, 0});
-        }
-    }
-    close_run();
+    Lv.wcnt = cnt;
+    make_wave_plan(Lv, P->lex_run_rows);
     return MGPCG_OK;
 }
 
@@ -256,10 +281,10 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(upload(&P->d_natoff[l], natoff, s));
         if (l == 0) ST_TRY(upload(&P->d_natoff0, natoff, s));
         if (P->smoother == MGPCG_SMOOTHER_SEQUENTIAL) {
-            int run_rows = 256;  // the largest wavefront a single-workgroup run takes
-            if (const char *env = getenv("MGPCG_LEX_RUN_ROWS"))  // tuning and test override, 0..512
-                run_rows = std::min(512, std::max(0, atoi(env)));
-            ST_TRY(build_waves(P, l, perm, iperm, run_rows, s));
+            if (l == 0)
+                if (const char *env = getenv("MGPCG_LEX_RUN_ROWS"))  // test override, 0..512
+                    P->lex_run_rows = std::min(512, std::max(0, atoi(env)));
+            ST_TRY(build_waves(P, l, perm, iperm, s));
         }
 
         // column bases for the compact column formats, per grid and colour:
@@ -305,26 +330,32 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         int64_t nt_bytes = (int64_t)128 << 20;  // operators above half the Infinity Cache are streamed
         if (const char *env = getenv("MGPCG_NT_BYTES")) nt_bytes = atoll(env);  // tuning override
         Lv.stream_nt = opbytes > nt_bytes;
-        // colour-pass tables: one workgroup per pass_block/R rows, grid-homogeneous
-        std::vector<Seg> tab;
-        Lv.pass_first.assign(Lv.ncol + 1, 0);
-        const int rows_per_block = pass_block(Lv.stream_nt) / R;
-        for (int k = 0; k < Lv.ncol; ++k) {
-            Lv.pass_first[k] = (int)tab.size();
-            for (int g = 0; g < G; ++g) {
-                const LevelGrid &lg = Lv.grids[g];
-                for (int64_t a = 0; a < lg.seg_len[k]; a += rows_per_block) {
-                    Seg e;
-                    e.row0 = lg.seg_off[k] + a;
-                    e.count = (int32_t)std::min<int64_t>(rows_per_block, lg.seg_len[k] - a);
-                    e.grid = (int16_t)g;
-                    e.colour = (int16_t)k;
-                    tab.push_back(e);
+        // colour-pass tables, for both workgroup sizes: one workgroup per
+        // pass_block/R rows, grid-homogeneous
+        for (int v = 0; v < 2; ++v) {
+            std::vector<Seg> tab;
+            std::vector<int> &first = Lv.pass_first_v[v];
+            first.assign(Lv.ncol + 1, 0);
+            const int rows_per_block = pass_block(v == 1) / R;
+            for (int k = 0; k < Lv.ncol; ++k) {
+                first[k] = (int)tab.size();
+                for (int g = 0; g < G; ++g) {
+                    const LevelGrid &lg = Lv.grids[g];
+                    for (int64_t a = 0; a < lg.seg_len[k]; a += rows_per_block) {
+                        Seg e;
+                        e.row0 = lg.seg_off[k] + a;
+                        e.count = (int32_t)std::min<int64_t>(rows_per_block, lg.seg_len[k] - a);
+                        e.grid = (int16_t)g;
+                        e.colour = (int16_t)k;
+                        tab.push_back(e);
+                    }
                 }
             }
+            first[Lv.ncol] = (int)tab.size();
+            ST_TRY(upload(&Lv.pass_tab_v[v], tab, s));
         }
-        Lv.pass_first[Lv.ncol] = (int)tab.size();
-        ST_TRY(upload(&Lv.pass_tab, tab, s));
+        Lv.pass_tab = Lv.pass_tab_v[Lv.stream_nt];
+        Lv.pass_first = Lv.pass_first_v[Lv.stream_nt];
 
         // zero-start forward pass: a colour-k row must skip every slot whose
         // real neighbour has colour >= k (not written yet in this sweep), and
@@ -521,13 +552,14 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         P->fuse_rz = G == 1 && R == 1 && P->mg_dtype == MGPCG_FP64 && L0.ncol == 8 &&
                      P->smoother == MGPCG_SMOOTHER_COLOURED;
         if (P->fuse_rz) {
-            const int rows = pass_block(L0.stream_nt) / R;
-            P->rz_off[0] = 0;
-            for (int k = 0; k < 8; ++k)
-                P->rz_off[k + 1] = P->rz_off[k] + (L0.coff[k + 1] - L0.coff[k] + rows - 1) / rows;
-            std::vector<int> gb = {0, (int)P->rz_off[8]};
-            ST_TRY(upload(&P->red_gb[2], gb, s));
-            max_blocks = std::max<int64_t>(max_blocks, P->rz_off[8]);
+            // the partials buffer serves either level-0 workgroup size
+            for (int v = 0; v < 2; ++v) {
+                int64_t off[9];
+                rz_layout(P, v == 1, off);
+                max_blocks = std::max<int64_t>(max_blocks, off[8]);
+            }
+            ST_TRY(dalloc(&P->red_gb[2], 2));
+            HIP_TRY(set_rz_layout(P, s));
         }
         const int64_t n0 = L0.n * R;
         ST_TRY(dalloc(&P->x, n0));
@@ -669,7 +701,9 @@ void free_problem(mgpcg_problem *P) {
         dfree(Lv.val64); dfree(Lv.val32); dfree(Lv.col); dfree(Lv.dcol); dfree(Lv.dbase); dfree(Lv.perm);
         dfree(Lv.grid_of_row);
         dfree(Lv.iperm);
-        dfree(Lv.grid_of_nat); dfree(Lv.pass_tab); dfree(Lv.inj_fine); dfree(Lv.inj_coarse);
+        dfree(Lv.grid_of_nat); dfree(Lv.pass_tab_v[0]); dfree(Lv.pass_tab_v[1]); dfree(Lv.inj_fine);
+        dfree(Lv.inj_coarse);
+        Lv.pass_tab = nullptr;
         dfree(Lv.r); dfree(Lv.z); dfree(Lv.t0); dfree(Lv.t1); dfree(Lv.t2);
         dfree(Lv.woff_dev); dfree(Lv.wrow); dfree(Lv.wcol); dfree(Lv.wval);
     }
@@ -740,7 +774,7 @@ template <typename T>
 hipError_t vcycle(const mgpcg_problem *P, const T *r0, T *z0, const int *done, hipStream_t s,
                   double *rzp = nullptr) {
     const bool persistent = P->coarse_ok && P->coarse_mode == 1;
-    const bool tail = !persistent && P->tail_ok;
+    const bool tail = !persistent && P->tail_ok && P->tail_on;
     // levels below L run one kernel per pass; the rest in one launch
     const int L = persistent ? P->coarse_lc : (tail ? P->tail_lw : P->L);
     auto rl = [&](int l) -> T * { return l == 0 ? const_cast<T *>(r0) : (T *)P->lev[l].r; };
@@ -951,6 +985,156 @@ mgpcg_status with_level_vectors(mgpcg_problem *p, int l, const double *r, double
         HIP_TRY(launch_cast_f2d((const float *)Lv.z, zi, n, s));
     }
     if (layout == MGPCG_LAYOUT_NATURAL) HIP_TRY(launch_permute(p, l, zi, z, false, s));
+    return MGPCG_OK;
+}
+
+// ------------------------------------------------------------ schedule
+
+mgpcg_schedule schedule_of(const mgpcg_problem *P) {
+    mgpcg_schedule S{};
+    S.graph = P->use_graph;
+    S.coarse_mode = P->coarse_mode;
+    S.coarse_tail = P->tail_on;
+    S.wide_levels = 0;
+    for (int l = 0; l < P->L; ++l)
+        if (P->lev[l].stream_nt) S.wide_levels |= 1u << l;
+    S.lex_run_rows = P->lex_run_rows;
+    return S;
+}
+
+bool same_schedule(const mgpcg_schedule &a, const mgpcg_schedule &b) {
+    return a.graph == b.graph && a.coarse_mode == b.coarse_mode && a.coarse_tail == b.coarse_tail &&
+           a.wide_levels == b.wide_levels && a.lex_run_rows == b.lex_run_rows;
+}
+
+mgpcg_status apply_schedule(mgpcg_problem *P, const mgpcg_schedule &S, hipStream_t s) {
+    if (S.graph != 0 && S.graph != 1) return fail(MGPCG_ERR_INVALID_ARG, "schedule.graph must be 0 or 1");
+    if (S.coarse_mode != 0 && S.coarse_mode != 1)
+        return fail(MGPCG_ERR_INVALID_ARG, "schedule.coarse_mode must be 0 or 1");
+    if (S.coarse_tail != 0 && S.coarse_tail != 1)
+        return fail(MGPCG_ERR_INVALID_ARG, "schedule.coarse_tail must be 0 or 1");
+    if (S.wide_levels >> P->L)
+        return fail(MGPCG_ERR_INVALID_ARG, "schedule.wide_levels has bits at or above the level count");
+    if (S.lex_run_rows < 0 || S.lex_run_rows > 512)
+        return fail(MGPCG_ERR_INVALID_ARG, "schedule.lex_run_rows must be in 0..512");
+    bool l0 = false;
+    for (int l = 0; l < P->L; ++l) {
+        Level &Lv = P->lev[l];
+        const bool wide = (S.wide_levels >> l) & 1u;
+        if (wide == Lv.stream_nt) continue;
+        Lv.stream_nt = wide;
+        Lv.pass_tab = Lv.pass_tab_v[wide];
+        Lv.pass_first = Lv.pass_first_v[wide];
+        if (l == 0) l0 = true;
+    }
+    if (l0 && P->fuse_rz) HIP_TRY(set_rz_layout(P, s));
+    P->use_graph = S.graph;
+    P->coarse_mode = S.coarse_mode;
+    P->tail_on = S.coarse_tail;
+    if (S.lex_run_rows != P->lex_run_rows) {
+        P->lex_run_rows = S.lex_run_rows;
+        if (P->smoother == MGPCG_SMOOTHER_SEQUENTIAL)
+            for (auto &Lv : P->lev) make_wave_plan(Lv, P->lex_run_rows);
+    }
+    if (P->iter_graph) {
+        (void)hipGraphExecDestroy(P->iter_graph);
+        P->iter_graph = nullptr;
+    }
+    return MGPCG_OK;
+}
+
+// what a tuned schedule depends on: the device kind and the problem's shape
+std::string problem_signature(const mgpcg_problem *P) {
+    hipDeviceProp_t prop;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, P->device) == hipSuccess)
+        dev = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    std::string k = "dev=" + dev + ";dims=";
+    for (int g = 0; g < P->G; ++g) {
+        if (g) k += ",";
+        k += std::to_string(P->dims0[3 * g]) + "x" + std::to_string(P->dims0[3 * g + 1]) + "x" +
+             std::to_string(P->dims0[3 * g + 2]);
+    }
+    k += ";levels=" + std::to_string(P->L) + ";nrhs=" + std::to_string(P->R) + ";mg_dtype=" +
+         std::to_string(P->mg_dtype) + ";colour_order=" + std::to_string(P->colour_order) + ";smoother=" +
+         std::to_string(P->smoother) + ";sweeps=" + std::to_string(P->sweeps);
+    return k;
+}
+
+// integer field `name` of one cache line; false if absent
+bool cache_field(const std::string &line, const char *name, long long *v) {
+    const std::string tag = std::string("\"") + name + "\": ";
+    const size_t at = line.find(tag);
+    if (at == std::string::npos) return false;
+    char *end = nullptr;
+    const char *p = line.c_str() + at + tag.size();
+    *v = strtoll(p, &end, 10);
+    return end != p;
+}
+
+// the last entry of the cache file for `key`, if any
+bool cache_lookup(const char *path, const std::string &key, mgpcg_schedule *S) {
+    std::ifstream f(path);
+    if (!f) return false;
+    const std::string want = "\"key\": \"" + key + "\"";
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        if (line.find(want) == std::string::npos) continue;
+        long long g, cm, ct, wl, lr;
+        if (!cache_field(line, "graph", &g) || !cache_field(line, "coarse_mode", &cm) ||
+            !cache_field(line, "coarse_tail", &ct) || !cache_field(line, "wide_levels", &wl) ||
+            !cache_field(line, "lex_run_rows", &lr))
+            continue;
+        S->graph = (int)g;
+        S->coarse_mode = (int)cm;
+        S->coarse_tail = (int)ct;
+        S->wide_levels = (unsigned)wl;
+        S->lex_run_rows = (int)lr;
+        found = true;
+    }
+    return found;
+}
+
+bool cache_append(const char *path, const std::string &key, const mgpcg_schedule &S, double ms, int iters) {
+    std::ofstream f(path, std::ios::app);
+    if (!f) return false;
+    f << "{\"key\": \"" << key << "\", \"graph\": " << S.graph << ", \"coarse_mode\": " << S.coarse_mode
+      << ", \"coarse_tail\": " << S.coarse_tail << ", \"wide_levels\": " << S.wide_levels
+      << ", \"lex_run_rows\": " << S.lex_run_rows << ", \"ms\": " << ms << ", \"iters\": " << iters << "}\n";
+    return (bool)f;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// best time in ms of `reps` runs of `iters` PCG iterations from x = 0 under
+// schedule S, after one warm-up run (b and x internal layout)
+mgpcg_status time_schedule(mgpcg_problem *P, const mgpcg_schedule &S, const double *b, double *x, int iters,
+                           int reps, hipStream_t s, double *best_ms) {
+    ST_TRY(apply_schedule(P, S, s));
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    const int64_t n = P->lev[0].n * P->R;
+    double best = 1e300;
+    for (int r = 0; r <= reps; ++r) {
+        HIP_TRY(launch_fill_d(x, n, 0.0, s));
+        HIP_TRY(hipEventRecord(ev.a, s));
+        ST_TRY(mgpcg_pcg_solve(P, b, x, iters, 0.0, nullptr, nullptr, MGPCG_LAYOUT_INTERNAL, s));
+        HIP_TRY(hipEventRecord(ev.b, s));
+        HIP_TRY(hipEventSynchronize(ev.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+        if (r > 0) best = std::min(best, (double)ms);
+    }
+    ST_TRY(device_error(P, s));
+    *best_ms = best;
     return MGPCG_OK;
 }
 
@@ -1326,6 +1510,117 @@ mgpcg_status mgpcg_set_coarse_mode(mgpcg_problem *p, int mode) {
         (void)hipGraphExecDestroy(p->iter_graph);
         p->iter_graph = nullptr;
     }
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_get_schedule(const mgpcg_problem *p, mgpcg_schedule *out) {
+    ST_TRY(check_problem(p));
+    if (!out) return fail(MGPCG_ERR_INVALID_ARG, "out is NULL");
+    *out = schedule_of(p);
+    return MGPCG_OK;
+}
+
+mgpcg_status mgpcg_set_schedule(mgpcg_problem *p, const mgpcg_schedule *sched, hipStream_t stream) {
+    ST_TRY(check_problem(p));
+    if (!sched) return fail(MGPCG_ERR_INVALID_ARG, "schedule is NULL");
+    DeviceGuard dg(p->device);
+    return apply_schedule(p, *sched, stream);
+}
+
+mgpcg_status mgpcg_autotune(mgpcg_problem *p, const double *b, int iters, int reps, const char *cache_path,
+                            mgpcg_schedule *chosen, hipStream_t s) {
+    ST_TRY(check_problem(p));
+    if (iters < 1 || iters > 1000) return fail(MGPCG_ERR_INVALID_ARG, "iters must be in 1..1000");
+    if (reps < 1 || reps > 100) return fail(MGPCG_ERR_INVALID_ARG, "reps must be in 1..100");
+    DeviceGuard dg(p->device);
+    const std::string key = problem_signature(p);
+    mgpcg_schedule S = schedule_of(p);
+    if (cache_path && cache_lookup(cache_path, key, &S)) {
+        ST_TRY(apply_schedule(p, S, s));
+        if (chosen) *chosen = schedule_of(p);
+        return MGPCG_OK;
+    }
+    // right-hand side and iterate in the internal layout, owned by this call
+    Level &L0 = p->lev[0];
+    const int64_t n = L0.n * p->R;
+    double *bi = nullptr, *xi = nullptr;
+    ST_TRY(dalloc(&bi, n));
+    mgpcg_status st = dalloc(&xi, n);
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        dfree(bi);
+        dfree(xi);
+    };
+    if (st != MGPCG_OK) {
+        cleanup();
+        return st;
+    }
+    hipError_t e = b ? launch_permute(p, 0, b, bi, true, s) : hipSuccess;
+    if (!b && e == hipSuccess) {
+        e = launch_fill_d(xi, n, 1.0, s);
+        if (e == hipSuccess) e = launch_spmv<double>(p, 0, L0.val64, xi, bi, s);
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "autotune: right-hand side");
+    }
+    const mgpcg_schedule start = S;
+    mgpcg_schedule best = S;
+    double best_ms = 0;
+    st = time_schedule(p, best, bi, xi, iters, reps, s, &best_ms);
+    auto consider = [&](const mgpcg_schedule &c) {
+        if (st != MGPCG_OK || same_schedule(c, best)) return;
+        double ms = 0;
+        st = time_schedule(p, c, bi, xi, iters, reps, s, &ms);
+        if (st == MGPCG_OK && ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    };
+    // graph replay or eager launches
+    {
+        mgpcg_schedule c = best;
+        c.graph ^= 1;
+        consider(c);
+    }
+    const bool coloured = p->smoother == MGPCG_SMOOTHER_COLOURED;
+    if (coloured) {
+        // coarse levels: per-pass kernels with or without the tail kernel,
+        // or the persistent kernel
+        for (int cm = 0; cm < 2; ++cm)
+            for (int ct = 0; ct < 2; ++ct) {
+                if (cm == 1 && !p->coarse_ok) continue;
+                if (ct == 1 && !p->tail_ok) continue;
+                mgpcg_schedule c = best;
+                c.coarse_mode = cm;
+                c.coarse_tail = ct;
+                consider(c);
+            }
+        // each level's workgroup choice; levels that the tail or persistent
+        // kernel runs have no colour-pass launches to tune
+        const bool persistent = p->coarse_ok && best.coarse_mode == 1;
+        const bool tail = !persistent && p->tail_ok && best.coarse_tail == 1;
+        const int lmax = persistent ? p->coarse_lc : (tail ? p->tail_lw : p->L);
+        for (int l = 0; l < lmax; ++l) {
+            if (l == 0 && p->fuse_rz) continue;  // would regroup the <r,z> partials
+            mgpcg_schedule c = best;
+            c.wide_levels ^= 1u << l;
+            consider(c);
+        }
+    } else {
+        for (int rr : {0, 64, 128, 256, 512}) {
+            mgpcg_schedule c = best;
+            c.lex_run_rows = rr;
+            consider(c);
+        }
+    }
+    if (st == MGPCG_OK) st = apply_schedule(p, best, s);
+    else (void)apply_schedule(p, start, s);
+    cleanup();
+    if (st != MGPCG_OK) return st;
+    if (cache_path && !cache_append(cache_path, key, best, best_ms, iters))
+        return fail(MGPCG_ERR_INVALID_ARG, std::string("autotune: cannot append to ") + cache_path);
+    if (chosen) *chosen = schedule_of(p);
     return MGPCG_OK;
 }
 

@@ -107,13 +107,20 @@ struct Level {
     int32_t *iperm = nullptr; // internal row -> natural packed row
     int32_t *grid_of_nat = nullptr;  // natural packed row -> grid (only when G > 1)
 
-    // colour-pass tables: entries of colour k are pass_tab[pass_first[k] .. pass_first[k+1])
+    // colour-pass tables: entries of colour k are pass_tab[pass_first[k] .. pass_first[k+1]);
+    // the active pair is variant [stream_nt] of pass_tab_v / pass_first_v
+    // (the segment length follows the workgroup size, pass_block(stream_nt))
     Seg *pass_tab = nullptr;
     std::vector<int> pass_first;
+    Seg *pass_tab_v[2] = {nullptr, nullptr};
+    std::vector<int> pass_first_v[2];
     uint32_t zi_skip[8] = {0};  // zero-start forward pass: slots whose neighbour is not yet written
     bool zs_ok = true;          // the zero-start pass is valid for every grid of the level
     bool zs_std = true;         // ... and its masks are the standard 8-colour ones (compiled in)
-    bool stream_nt = true;      // operator larger than the caches: stream it with non-temporal loads
+    // the colour passes use 256-thread workgroups and stream the operator with
+    // non-temporal loads (set by default when it is larger than the caches);
+    // otherwise one-wave workgroups and cached loads.  A schedule choice.
+    bool stream_nt = true;
     bool fuse_transfers = false;  // colour 0 is exactly the injection set, in injection order, and is
                                   // swept last by the pre- and first by the post-smoother
 
@@ -130,6 +137,7 @@ struct Level {
     int nwave = 0;
     int64_t npos = 0;
     std::vector<int64_t> woff;
+    std::vector<int64_t> wcnt;   // rows of each wavefront (unpadded)
     int64_t *woff_dev = nullptr;
     int32_t *wrow = nullptr;
     int32_t *wcol = nullptr;
@@ -188,6 +196,7 @@ struct mgpcg_problem {
     int colour_order = 0;
     int smoother = MGPCG_SMOOTHER_COLOURED;
     int sweeps = 1;  // symmetric sweeps per smoothing step of the V-cycle
+    int lex_run_rows = 256;  // sequential smoother: largest wavefront a single-workgroup run takes
     // most compact column format allowed (Level::cf), 2 by default
     int col_format = 2;
     std::vector<int> dims0;  // 3*G, level 0
@@ -229,6 +238,7 @@ struct mgpcg_problem {
     unsigned *coarse_flags = nullptr;   // coarse_blocks + 1 (last: epoch base)
     // coarsest level in one workgroup with r and z in LDS
     bool tail_ok = false;
+    int tail_on = 1;           // schedule choice: use the tail kernel when tail_ok
     int tail_lw = 0;
     int *coarse_err = nullptr;
 

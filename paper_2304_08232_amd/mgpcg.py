@@ -27,8 +27,8 @@ ABI_FUNCTIONS = [
     "mgpcg_to_natural", "mgpcg_spmv", "mgpcg_make_rhs_ones", "mgpcg_gs_sweep", "mgpcg_colour_pass",
     "mgpcg_restrict",
     "mgpcg_prolong_add", "mgpcg_mg_vcycle", "mgpcg_pcg_solve", "mgpcg_solve_result",
-    "mgpcg_theta_grad", "mgpcg_set_graph_mode", "mgpcg_set_coarse_mode", "mgpcg_check",
-    "mgpcg_last_error",
+    "mgpcg_theta_grad", "mgpcg_set_graph_mode", "mgpcg_set_coarse_mode", "mgpcg_get_schedule",
+    "mgpcg_set_schedule", "mgpcg_autotune", "mgpcg_check", "mgpcg_last_error",
 ]
 
 
@@ -36,6 +36,15 @@ class MGPCGError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class _Schedule(C.Structure):
+    _fields_ = [("graph", C.c_int), ("coarse_mode", C.c_int), ("coarse_tail", C.c_int),
+                ("wide_levels", C.c_uint), ("lex_run_rows", C.c_int)]
+
+
+def _sched_dict(s):
+    return {name: int(getattr(s, name)) for name, _ in _Schedule._fields_}
 
 
 class _Config(C.Structure):
@@ -78,6 +87,9 @@ def lib():
         L.mgpcg_theta_grad.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mgpcg_set_graph_mode.argtypes = [vp, i32]
         L.mgpcg_set_coarse_mode.argtypes = [vp, i32]
+        L.mgpcg_get_schedule.argtypes = [vp, C.POINTER(_Schedule)]
+        L.mgpcg_set_schedule.argtypes = [vp, C.POINTER(_Schedule), vp]
+        L.mgpcg_autotune.argtypes = [vp, vp, i32, i32, C.c_char_p, C.POINTER(_Schedule), vp]
         L.mgpcg_check.argtypes = [vp, vp]
         _lib = L
     return _lib
@@ -197,6 +209,25 @@ def mgpcg_set_graph_mode(h, on):
 
 def mgpcg_set_coarse_mode(h, mode):
     return _check(lib().mgpcg_set_coarse_mode(C.c_void_p(h), int(mode)))
+
+
+def mgpcg_get_schedule(h):
+    s = _Schedule()
+    _check(lib().mgpcg_get_schedule(C.c_void_p(h), C.byref(s)))
+    return _sched_dict(s)
+
+
+def mgpcg_set_schedule(h, sched, stream=None):
+    s = _Schedule(**{k: int(v) for k, v in sched.items()})
+    return _check(lib().mgpcg_set_schedule(C.c_void_p(h), C.byref(s), _stream(stream)))
+
+
+def mgpcg_autotune(h, b=None, iters=10, reps=3, cache_path=None, stream=None):
+    s = _Schedule()
+    _check(lib().mgpcg_autotune(C.c_void_p(h), None if b is None else _ptr(b), int(iters), int(reps),
+                                None if cache_path is None else os.fsencode(cache_path), C.byref(s),
+                                _stream(stream)))
+    return _sched_dict(s)
 
 
 def mgpcg_check(h, stream=None):
@@ -328,6 +359,21 @@ class Problem:
 
     def check(self):
         return mgpcg_check(self.h)
+
+    @property
+    def schedule(self):
+        """The execution schedule (mgpcg_schedule) as a dict."""
+        return mgpcg_get_schedule(self.h)
+
+    def set_schedule(self, **fields):
+        """Change some fields of the schedule; the rest keep their values."""
+        s = self.schedule
+        s.update(fields)
+        mgpcg_set_schedule(self.h, s)
+
+    def autotune(self, b=None, iters=10, reps=3, cache_path=None):
+        """Time candidate schedules, apply the fastest; returns it."""
+        return mgpcg_autotune(self.h, b, iters, reps, cache_path)
 
 
 class MGPCGSolve(torch.autograd.Function):

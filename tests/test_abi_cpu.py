@@ -66,6 +66,10 @@ def test_argument_errors_without_device():
     assert L.mgpcg_spmv(None, 0, None, None, 0, None) == -1
     assert L.mgpcg_colour_pass(None, 0, 0, None, None, 0, None) == -1
     assert L.mgpcg_pcg_solve(None, None, None, 10, C.c_double(0.0), None, None, 0, None) == -1
+    sch = mgpcg._Schedule()
+    assert L.mgpcg_get_schedule(None, C.byref(sch)) == -1
+    assert L.mgpcg_set_schedule(None, C.byref(sch), None) == -1
+    assert L.mgpcg_autotune(None, None, 10, 3, None, C.byref(sch), None) == -1
     assert L.mgpcg_last_error()
 
 
