@@ -17,7 +17,10 @@ Also reported on the same line:
                 sequential (wavefront) smoother against the coloured one,
                 1-3 sweeps per smoothing step, and an HPCG-style validation
                 (symmetry departures, iterations to match 50 sequential-
-                smoother iterations, timed fixed-iteration sets).
+                smoother iterations, timed fixed-iteration sets).  The
+                batched and multi-RHS solves run under the schedule the
+                autotuner picks; the default schedule's times are reported
+                beside them, and the autotuner's pick for the 128^3 problem.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extensions]
        [--no-cpu-baseline] [--only-kernel]
@@ -57,16 +60,26 @@ def measured_traffic(per_launch_alg_bytes):
 
 
 def time_solves(torch, mg, prob, b, x, steps, warmup, iters):
+    """Mean wall time per step over `steps` solves, and the standard deviation
+    of the per-step times taken from HIP events recorded between the steps on
+    the stream the solves run on (no host synchronisation inside the timed
+    region)."""
     for _ in range(warmup):
         x.zero_()
         prob.solve_async(b, x, max_iters=iters, layout=mg.INTERNAL)
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         x.zero_()  # x0 = 0 for every step
         prob.solve_async(b, x, max_iters=iters, layout=mg.INTERNAL)
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    t = (time.perf_counter() - t0) / steps
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    std = float(np.std(per, ddof=1)) if steps > 1 else 0.0
+    return t, std
 
 
 def time_to_tol(torch, prob, b, tol, max_iters=1000, reps=3):
@@ -152,6 +165,10 @@ def extensions(torch, mg):
     sizes = [a * b_ * c for a, b_, c in dims_list]
     bb = torch.tensor(inputs.batch_rhs(44, sizes), device="cuda")
     pb = mg.Problem(dims_list, levels=LEVELS)
+    tb_default, (xb, hb, itb, stb) = time_to_tol(torch, pb, bb, 1e-9)
+    # the schedule of the batched solve is the autotuner's pick (its results
+    # are bit-identical under every schedule it tries)
+    tuned_b = pb.autotune(bb, iters=10, reps=3)
     tb, (xb, hb, itb, stb) = time_to_tol(torch, pb, bb, 1e-9)
     pb.close()
     tsum, its_single = 0.0, []
@@ -164,7 +181,8 @@ def extensions(torch, mg):
         off += n
         ps.close()
     ext["batched_64_grids"] = {
-        "total_rows": int(sum(sizes)), "batched_s": round(tb, 5), "sum_single_s": round(tsum, 5),
+        "total_rows": int(sum(sizes)), "batched_s": round(tb, 5), "batched_s_default_schedule": round(tb_default, 5),
+        "schedule": tuned_b, "sum_single_s": round(tsum, 5),
         "speedup": round(tsum / tb, 3), "iters_batched": [int(v) for v in itb],
         "iters_match_single": bool(list(map(int, itb)) == its_single),
         "all_converged": bool(stb == mg.OK)}
@@ -176,6 +194,8 @@ def extensions(torch, mg):
     n = GRID[0] ** 3
     B = torch.tensor(inputs.multi_rhs(41, 16, n), device="cuda")
     pm = mg.Problem(GRID, levels=LEVELS, nrhs=16)
+    tm_default, (xm, hm, itm, stm) = time_to_tol(torch, pm, B, 1e-9)
+    tuned_m = pm.autotune(B, iters=5, reps=3)
     tm, (xm, hm, itm, stm) = time_to_tol(torch, pm, B, 1e-9)
     pm.close()
     ps = mg.Problem(GRID, levels=LEVELS)
@@ -187,7 +207,8 @@ def extensions(torch, mg):
         its_single.append(int(its_[0]))
     ps.close()
     ext["multi_rhs_16_128cubed"] = {
-        "multi_s": round(tm, 5), "sum_single_s": round(tsum, 5), "speedup": round(tsum / tm, 3),
+        "multi_s": round(tm, 5), "multi_s_default_schedule": round(tm_default, 5), "schedule": tuned_m,
+        "sum_single_s": round(tsum, 5), "speedup": round(tsum / tm, 3),
         "iters": [int(v) for v in itm], "iters_match_single": bool(list(map(int, itm)) == its_single),
         "all_converged": bool(stm == mg.OK)}
     log("multi-rhs:", {k: v for k, v in ext["multi_rhs_16_128cubed"].items() if k != "iters"})
@@ -275,6 +296,20 @@ def extensions(torch, mg):
             log("smoother sweeps:", dims, name, row)
 
     ext["hpcg_validation"] = hpcg_validation(torch, mg, inputs)
+
+    # the autotuner on the benchmark's own problem: 50-iteration solves under
+    # the default and the tuned schedule (bit-identical results)
+    pa = mg.Problem(GRID, levels=LEVELS)
+    ba = pa.make_rhs_ones(layout=mg.INTERNAL)
+    xa = torch.zeros_like(ba)
+    default = pa.schedule
+    t_def, _ = time_solves(torch, mg, pa, ba, xa, 10, 2, ITERS)
+    tuned = pa.autotune(None, iters=10, reps=3)
+    t_tuned, _ = time_solves(torch, mg, pa, ba, xa, 10, 2, ITERS)
+    pa.close()
+    ext["autotune_128cubed"] = {"default_schedule": default, "tuned_schedule": tuned,
+                                "default_ms_per_50": round(t_def * 1e3, 3), "tuned_ms_per_50": round(t_tuned * 1e3, 3)}
+    log("autotune 128^3:", ext["autotune_128cubed"])
     return ext
 
 
@@ -386,7 +421,8 @@ def main():
 
     b = prob.make_rhs_ones(layout=mg.INTERNAL)
     x = prob.zeros()
-    t_step = time_to_solve = time_solves(torch, mg, prob, b, x, args.steps, args.warmup, ITERS)
+    t_step, t_std_ms = time_solves(torch, mg, prob, b, x, args.steps, args.warmup, ITERS)
+    time_to_solve = t_step
     hist = np.zeros(ITERS)
     its = np.zeros(1, np.int32)
     st = mg.mgpcg_solve_result(prob.h, ITERS, hist, its)
@@ -410,6 +446,7 @@ def main():
     line = {
         "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 4),
+        "ms_per_step_std": round(t_std_ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "fp64_mgpcg_128cubed_50it", "grid": list(GRID), "levels": LEVELS,
