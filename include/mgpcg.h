@@ -85,9 +85,10 @@ typedef struct {
                             (t = ix + 2 iy + 4 iz).  Requires mg_dtype
                             MGPCG_FP64 and nrhs 1. */
     int sweeps;          /* symmetric sweeps per smoothing step of the V-cycle
-                            (Listing 1, lines 2 and 10, and the coarsest
-                            level), 0..MGPCG_MAX_SWEEPS; 0 means 1, the
-                            default of the paper's experiments (Sec. V). */
+                            (the pre- and post-smoothing of Listing 1, and
+                            the coarsest level's), 0..MGPCG_MAX_SWEEPS; 0
+                            means 1, the default of the paper's experiments
+                            (Sec. V). */
 } mgpcg_config;
 
 /* Sec. II-A/B, II-D, III-A: build the level hierarchy on the current device:

@@ -353,7 +353,7 @@ void ora_sgs_lex(const ora_hier *h, int level, const double *r, double *z) {
 }
 
 /*
- * The smoother of Listing 1 (its lines 2 and 10): h->sweeps symmetric sweeps
+ * The smoother of Listing 1 (pre- and post-smoothing): h->sweeps symmetric sweeps
  * in a row (Sec. V notes that several runs may help convergence; one is the
  * default), coloured or sequential.
  */

@@ -1,7 +1,7 @@
 """GPU parity with several symmetric sweeps per smoothing step.
 
-Each smoothing step of the V-cycle (Listing 1, lines 2 and 10, and the
-coarsest level) runs `sweeps` symmetric sweeps.  The library fuses the
+Each smoothing step of the V-cycle (the pre- and post-smoothing of Listing 1,
+and the coarsest level's) runs `sweeps` symmetric sweeps.  The library fuses the
 restriction into the last pre-smoothing sweep, the refinement into the first
 post-smoothing sweep and the <r,z> partials into the last one; the oracle
 runs the steps one after another.  V-cycles compare bit for bit, PCG
