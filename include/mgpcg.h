@@ -259,7 +259,8 @@ mgpcg_status mgpcg_set_schedule(mgpcg_problem *p, const mgpcg_schedule *sched, h
  * timing, otherwise the chosen one is appended.  *chosen (HOST, may be NULL)
  * receives the applied schedule.  iters in 1..1000, reps in 1..100.
  * Allocates two vectors of the level-0 size for the duration of the call and
- * synchronises the stream. */
+ * synchronises the stream.  The timed runs are solves on this problem: a
+ * later mgpcg_solve_result reports the last of them, not an earlier solve. */
 mgpcg_status mgpcg_autotune(mgpcg_problem *p, const double *b, int iters, int reps, const char *cache_path,
                             mgpcg_schedule *chosen, hipStream_t stream);
 
