@@ -43,8 +43,9 @@ def host(t):
 
 
 @pytest.mark.parametrize("run_rows", RUN_ROWS)
-@pytest.mark.parametrize("dims", [(16, 16, 16), (24, 16, 32), (8, 8, 56)])
+@pytest.mark.parametrize("dims", [(16, 16, 16), (24, 16, 32), (8, 8, 56), (24, 40, 24)])
 def test_sweep_bitwise_each_level(mg, dims, run_rows, monkeypatch):
+    # (24, 40, 24) has odd extents at level 3
     monkeypatch.setenv("MGPCG_LEX_RUN_ROWS", run_rows)
     print(f"sequential sweep {dims} run_rows={run_rows}", flush=True)
     o = Oracle(*dims, levels=4)
@@ -75,13 +76,14 @@ def test_sweep_small_and_flat_grids(mg, dims, run_rows, monkeypatch):
     np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle_lex(r))
 
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("run_rows", RUN_ROWS)
 @pytest.mark.parametrize("dims", [(16, 16, 16), (24, 16, 32)])
-def test_vcycle_bitwise(mg, dims, run_rows, monkeypatch):
+def test_vcycle_bitwise(mg, dims, run_rows, order, monkeypatch):
     monkeypatch.setenv("MGPCG_LEX_RUN_ROWS", run_rows)
-    print(f"sequential V-cycle {dims} run_rows={run_rows}", flush=True)
-    o = Oracle(*dims, levels=4)
-    p = mg.Problem(dims, levels=4, smoother="sequential")
+    print(f"sequential V-cycle {dims} run_rows={run_rows} order={order}", flush=True)
+    o = Oracle(*dims, levels=4, colour_order=order)
+    p = mg.Problem(dims, levels=4, smoother="sequential", colour_order=order)
     for seed in (1, 2):
         r = inputs.uniform(seed, o.n())
         np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle_lex(r))
