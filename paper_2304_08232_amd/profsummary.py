@@ -12,6 +12,8 @@
       WRITE_SIZE run, each counter scaled by what it reads for the largest
       device copy in the same run (a copy of --copy-mib MiB); --json writes
       the figure with the hash of the kernel sources it was taken on
+  python -m paper_2304_08232_amd.profsummary traffic-all FETCH_DIR WRITE_DIR [--copy-mib 512] [--cmd "..."]
+      the same for every (kernel, grid size) of the two runs, largest first
 """
 import argparse
 import csv
@@ -118,6 +120,35 @@ def traffic(fetch_dir, write_dir, kernel, grid, copy_mib=512):
     return res
 
 
+def traffic_all(fetch_dir, write_dir, copy_mib=512):
+    """{(kernel, grid): (dispatches, fetch bytes, write bytes)} per dispatch, scaled."""
+    acc = defaultdict(lambda: [0, 0.0, 0.0])
+    for col, d, counter in ((1, fetch_dir, "FETCH_SIZE"), (2, write_dir, "WRITE_SIZE")):
+        rows = _counter_rows(d, counter)
+        copies = [v for n, g, v in rows if "copyBuffer" in n]
+        if not copies:
+            raise SystemExit(f"{counter}: no copy in {d}")
+        factor = copy_mib * 1024.0 / max(copies)
+        for n, g, v in rows:
+            if "copyBuffer" in n:
+                continue
+            a = acc[(_short(n), g)]
+            if col == 1:
+                a[0] += 1
+            a[col] += 1024.0 * v * factor
+    return {k: (a[0], a[1] / max(a[0], 1), a[2] / max(a[0], 1)) for k, a in acc.items()}
+
+
+def traffic_all_summary(t, cmd):
+    out = ["# rocprofv3 counter summary: HBM bytes per dispatch of every kernel",
+           "# (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a device copy of known size)",
+           f"# commands: {cmd}", "",
+           f"{'kernel':58s} {'grid':>9s} {'calls':>6s} {'read_MB':>9s} {'write_MB':>9s} {'total_MB':>9s}"]
+    for (name, grid), (n, f, w) in sorted(t.items(), key=lambda kv: -(kv[1][1] + kv[1][2]) * kv[1][0]):
+        out.append(f"{name[:58]:58s} {grid:9d} {n:6d} {f / 1e6:9.2f} {w / 1e6:9.2f} {(f + w) / 1e6:9.2f}")
+    return "\n".join(out)
+
+
 def traffic_summary(t, cmd):
     return "\n".join([
         "# rocprofv3 counter summary: HBM traffic of one kernel",
@@ -133,7 +164,7 @@ def traffic_summary(t, cmd):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "pmc", "traffic"])
+    ap.add_argument("mode", choices=["trace", "pmc", "traffic", "traffic-all"])
     ap.add_argument("dir")
     ap.add_argument("args", nargs="*")
     ap.add_argument("--cmd", default="")
@@ -144,6 +175,8 @@ def main():
         print(trace_summary(a.dir, a.cmd))
     elif a.mode == "pmc":
         print(pmc_summary(a.dir, a.args[0], int(a.args[1]), a.cmd))
+    elif a.mode == "traffic-all":
+        print(traffic_all_summary(traffic_all(a.dir, a.args[0], a.copy_mib), a.cmd))
     else:
         t = traffic(a.dir, a.args[0], a.args[1], int(a.args[2]), a.copy_mib)
         t["command"] = a.cmd
