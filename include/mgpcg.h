@@ -130,10 +130,13 @@ mgpcg_status mgpcg_spmv(const mgpcg_problem *p, int level, const double *x, doub
 mgpcg_status mgpcg_make_rhs_ones(const mgpcg_problem *p, double *b, int layout, hipStream_t stream);
 
 /* Sec. III-A, Listings 2-3 (forward pass) and Sec. II-E (symmetric form):
- * one symmetric coloured Gauss-Seidel sweep at `level`, in place on z:
- * colours 0..c-1, then c-1..0; for each row i of the colour being swept
+ * one symmetric sweep of the problem's smoother at `level`, in place on z
+ * (one sweep, whatever the config's `sweeps`).  Coloured: colours 0..c-1,
+ * then c-1..0; for each row i of the colour being swept
  * z_i <- (r_i - sum_j a_ij z_j + z_i a_ii) / a_ii with the sum over the whole
- * row.  Runs in the V-cycle precision.  r and z must not overlap. */
+ * row.  Sequential (Eq. (1)): rows in increasing, then decreasing natural
+ * order, z_i <- (r_i - sum_{j != i} a_ij z_j) / a_ii with every z_j as last
+ * updated.  Runs in the V-cycle precision.  r and z must not overlap. */
 mgpcg_status mgpcg_gs_sweep(const mgpcg_problem *p, int level, const double *r, double *z, int layout,
                             hipStream_t stream);
 
@@ -159,9 +162,10 @@ mgpcg_status mgpcg_restrict(const mgpcg_problem *p, int level, const double *r, 
 mgpcg_status mgpcg_prolong_add(const mgpcg_problem *p, int level, const double *zc, double *z,
                                int layout, hipStream_t stream);
 
-/* Sec. II-D, Listing 1: z = M^{-1} r, one V-cycle from z = 0: symmetric sweep,
- * restriction, recursion, refinement, symmetric sweep; the coarsest level does
- * one symmetric sweep.  r and z are level-0 vectors. */
+/* Sec. II-D, Listing 1: z = M^{-1} r, one V-cycle from z = 0: smoothing,
+ * restriction, recursion, refinement, smoothing; the coarsest level only
+ * smooths.  Each smoothing step is `sweeps` symmetric sweeps of the
+ * problem's smoother.  r and z are level-0 vectors. */
 mgpcg_status mgpcg_mg_vcycle(const mgpcg_problem *p, const double *r, double *z, int layout,
                              hipStream_t stream);
 
