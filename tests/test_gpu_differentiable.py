@@ -91,3 +91,38 @@ def test_gradient_matches_oracle_adjoint_16cubed(mg):
     go = Oracle.theta_grad(lam, xo, theta)
     np.testing.assert_allclose(g, go, rtol=1e-8, atol=1e-10 * np.abs(go).max())
     np.testing.assert_allclose(gb, lam, rtol=1e-8, atol=1e-10 * np.abs(lam).max())
+
+
+def test_theta_with_batched_grids_rhs_and_fp32(mg):
+    # theta is one value per level-0 point, packed over grids in natural
+    # order and shared by the right-hand sides of a grid; softplus may differ
+    # in the last bit between device and host, so V-cycles agree to 1e-12
+    dims = [(16, 16, 16), (24, 16, 32), (8, 16, 8)]
+    sizes = [a * b * c for a, b, c in dims]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    theta = inputs.uniform(71, int(offs[-1]), -3.0, 3.0)
+    r = inputs.batch_rhs(72, sizes)
+    p = mg.Problem(dims, levels=4, theta=torch.tensor(theta, device="cuda"))
+    z = p.vcycle(torch.tensor(r, device="cuda")).cpu().numpy()
+    y = p.spmv(torch.tensor(r, device="cuda")).cpu().numpy()
+    for g, d in enumerate(dims):
+        o = Oracle(*d, levels=4, theta=theta[offs[g]:offs[g + 1]])
+        rg = r[offs[g]:offs[g + 1]]
+        ref = o.vcycle(rg)
+        np.testing.assert_allclose(z[offs[g]:offs[g + 1]], ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+        np.testing.assert_allclose(y[offs[g]:offs[g + 1]], o.spmv(rg), rtol=1e-14, atol=1e-14)
+    # four right-hand sides on one grid share its theta
+    n = 16 ** 3
+    th = theta[:n]
+    o = Oracle(16, 16, 16, levels=4, theta=th)
+    B = inputs.multi_rhs(73, 4, n)
+    p4 = mg.Problem((16, 16, 16), levels=4, nrhs=4, theta=torch.tensor(th, device="cuda"))
+    Z = p4.vcycle(torch.tensor(B, device="cuda")).cpu().numpy()
+    for v in range(4):
+        ref = o.vcycle(B[v * n:(v + 1) * n])
+        np.testing.assert_allclose(Z[v * n:(v + 1) * n], ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+    # the FP32 V-cycle rounds the theta diagonal to FP32 like the oracle does
+    p32 = mg.Problem((16, 16, 16), levels=4, mg_dtype="fp32", theta=torch.tensor(th, device="cuda"))
+    z32 = p32.vcycle(torch.tensor(B[:n], device="cuda")).cpu().numpy()
+    ref32 = o.vcycle32(B[:n])
+    np.testing.assert_allclose(z32, ref32, rtol=1e-6, atol=1e-7 * np.abs(ref32).max())
