@@ -251,10 +251,11 @@ def test_fp32_pcg_matches_oracle(mg):
 
 # -------------------------------------------------------- batched / multi-RHS
 
-def test_batched_grids(mg):
+@pytest.mark.parametrize("order", [0, 1])
+def test_batched_grids(mg, order):
     dims = [(16, 16, 16), (24, 16, 32), (8, 16, 8)]
-    p = mg.Problem(dims, levels=4)
-    oras = [Oracle(*d) for d in dims]
+    p = mg.Problem(dims, levels=4, colour_order=order)
+    oras = [Oracle(*d, colour_order=order) for d in dims]
     sizes = [o.n() for o in oras]
     offs = np.concatenate([[0], np.cumsum(sizes)])
     b = inputs.batch_rhs(9, sizes)
@@ -282,12 +283,13 @@ def test_batched_grids(mg):
         np.testing.assert_allclose(xg[offs[g]:offs[g + 1]], xo, rtol=0, atol=1e-12 * np.abs(xo).max())
 
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("nrhs", [2, 16])
-def test_multi_rhs(mg, nrhs):
+def test_multi_rhs(mg, nrhs, order):
     dims = (16, 16, 16)
-    o = Oracle(*dims)
+    o = Oracle(*dims, colour_order=order)
     n = o.n()
-    p = mg.Problem(dims, nrhs=nrhs)
+    p = mg.Problem(dims, nrhs=nrhs, colour_order=order)
     B = inputs.multi_rhs(41, nrhs, n)
     Z = host(p.vcycle(dev(B)))
     Y = host(p.spmv(dev(B)))
