@@ -284,6 +284,29 @@ def test_batched_grids(mg, order):
 
 
 @pytest.mark.parametrize("order", [0, 1])
+def test_fp32_vcycle_batched_and_multi_rhs(mg, order):
+    # the FP32 V-cycle on several grids and on 4 and 16 right-hand sides,
+    # bit for bit with the oracle's FP32 V-cycle of each grid / rhs
+    dims = [(16, 16, 16), (24, 16, 32), (8, 16, 8)]
+    sizes = [a * b * c for a, b, c in dims]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    r = inputs.batch_rhs(81, sizes)
+    p = mg.Problem(dims, levels=4, mg_dtype="fp32", colour_order=order)
+    z = host(p.vcycle(dev(r)))
+    for g, d in enumerate(dims):
+        o = Oracle(*d, colour_order=order)
+        np.testing.assert_array_equal(z[offs[g]:offs[g + 1]], o.vcycle32(r[offs[g]:offs[g + 1]]))
+    o = Oracle(16, 16, 16, colour_order=order)
+    n = o.n()
+    for nrhs in (4, 16):
+        B = inputs.multi_rhs(82, nrhs, n)
+        pm = mg.Problem((16, 16, 16), nrhs=nrhs, mg_dtype="fp32", colour_order=order)
+        Z = host(pm.vcycle(dev(B)))
+        for v in range(nrhs):
+            np.testing.assert_array_equal(Z[v * n:(v + 1) * n], o.vcycle32(B[v * n:(v + 1) * n]))
+
+
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("nrhs", [2, 16])
 def test_multi_rhs(mg, nrhs, order):
     dims = (16, 16, 16)

@@ -59,6 +59,18 @@ def test_sequential_vcycle_bitwise(mg, sweeps):
     np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle_lex(r))
 
 
+def test_sequential_batched_two_sweeps(mg):
+    dims = [(16, 16, 16), (24, 16, 32), (8, 16, 8)]
+    sizes = [a * b * c for a, b, c in dims]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    r = inputs.batch_rhs(83, sizes)
+    p = mg.Problem(dims, levels=4, smoother="sequential", sweeps=2)
+    z = host(p.vcycle(dev(r)))
+    for g, d in enumerate(dims):
+        o = Oracle(*d, sweeps=2)
+        np.testing.assert_array_equal(z[offs[g]:offs[g + 1]], o.vcycle_lex(r[offs[g]:offs[g + 1]]))
+
+
 def test_one_sweep_is_the_default(mg):
     dims = (16, 16, 16)
     r = dev(inputs.uniform(4, 16 ** 3))
