@@ -53,6 +53,9 @@ def test_argument_errors_without_device():
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], dtype=1, smoother=1)), None, C.byref(h)) == -1
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], nrhs=2, smoother=1)), None, C.byref(h)) == -1
     assert b"sequential smoother" in L.mgpcg_last_error()
+    # the 32-bit row-index limit: 27 n < 2^31
+    assert L.mgpcg_create(C.byref(_cfg([(448, 448, 448)], levels=1)), None, C.byref(h)) == -2
+    assert b"too large" in L.mgpcg_last_error()
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], sweeps=-1)), None, C.byref(h)) == -1
     assert L.mgpcg_create(C.byref(_cfg([(16, 16, 16)], sweeps=17)), None, C.byref(h)) == -1
     assert b"sweeps" in L.mgpcg_last_error()

@@ -104,6 +104,31 @@ def test_vcycle_bitwise(mg, dims, order):
         np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle(r))
 
 
+@pytest.mark.parametrize("dims,levels", [((1, 1, 1), 1), ((5, 1, 1), 1), ((1, 7, 1), 1), ((3, 1, 5), 1),
+                                         ((2, 9, 1), 1), ((8, 8, 8), 4), ((16, 16, 8), 4)])
+@pytest.mark.parametrize("order", [0, 1])
+def test_degenerate_grids(mg, dims, levels, order):
+    # one point, flat grids (fewer colours: the parity bits of extent-1
+    # dimensions are dropped), and hierarchies whose coarsest level is
+    # 1x1x1 (8^3) or flat 2x2x1 (16x16x8)
+    o = Oracle(*dims, levels=levels, colour_order=order)
+    p = mg.Problem(dims, levels=levels, colour_order=order)
+    for l in range(levels):
+        n = o.n(l)
+        x, z0 = inputs.uniform(90 + l, n), inputs.uniform(95 + l, n)
+        np.testing.assert_array_equal(host(p.spmv(dev(x), level=l)), o.spmv(x, level=l))
+        np.testing.assert_array_equal(host(p.gs_sweep(dev(x), dev(z0), level=l)), o.sgs(x, z0, level=l))
+        for k in range(o.ncolours(l)):
+            np.testing.assert_array_equal(host(p.colour_pass(dev(x), dev(z0), k, level=l)),
+                                          o.colour_pass(k, x, z0, level=l))
+    r = inputs.uniform(99, o.n())
+    np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle(r))
+    xo, ho, ito, sto = o.pcg(r, max_iters=30, tol=1e-10)
+    x, h, its, st = p.solve(dev(r), max_iters=30, tol=1e-10)
+    assert st == sto and its[0] == ito
+    assert_history_close(h[0, :ito], ho)
+
+
 def test_rhs_ones(mg):
     o = Oracle(16, 16, 16)
     p = mg.Problem((16, 16, 16))
