@@ -24,6 +24,26 @@
  *   workspaces are owned by the problem handle.
  * - Streams are HIP streams (NULL = the legacy default stream).  Calls are
  *   asynchronous on the stream unless stated otherwise.
+ * - A handle's workspaces (permutation buffers, level vectors, CG vectors,
+ *   reduction partials, captured graphs) are shared by all calls on it.  Calls
+ *   on one handle must therefore be ordered: issue them on one stream, or
+ *   synchronise between the streams used.  Do not call on one handle from
+ *   several host threads at once.  Separate handles are independent.
+ * - Environment overrides, read by mgpcg_create, for tuning and tests.  None
+ *   changes the arithmetic:
+ *     MGPCG_DELTA_COLS     cap on the column format: 0 int32 columns, 1 int8
+ *                          deltas, 2 (default) implied columns where possible
+ *     MGPCG_NT_BYTES       operators larger than this use 256-thread
+ *                          workgroups and non-temporal loads (default 128 MiB)
+ *     MGPCG_TAIL_BYTES     largest coarsest level (r and z bytes) run in one
+ *                          workgroup (default and maximum 64 KiB)
+ *     MGPCG_COARSE_BLOCKS  workgroups of the persistent coarse kernel
+ *                          (1..number of CUs)
+ *     MGPCG_LEX_RUN_ROWS   largest wavefront a single-workgroup run of the
+ *                          sequential smoother takes (0..512, default 256)
+ *   MGPCG_NT_BYTES also regroups the partial sums of <r,z> when that product
+ *   is fused into the level-0 smoother (the same caveat as wide_levels in
+ *   mgpcg_schedule).
  * - A problem holds G >= 1 independent grids ("batched problems") with R >= 1
  *   right-hand sides each, i.e. S = G*R systems.  Vectors at level l are packed
  *   grid after grid; within a grid, right-hand side after right-hand side;
