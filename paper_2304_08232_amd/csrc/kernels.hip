@@ -1362,6 +1362,13 @@ __device__ __forceinline__ Seg vec_seg(const Seg *__restrict__ tab, int blk, int
     return e;
 }
 
+// SpMV-type kernels (one row per R threads, table 0): with one right-hand
+// side a workgroup takes one table entry of kBlock rows.  With R > 1 an entry
+// holds only kBlock/R rows, so a workgroup takes `spc` consecutive entries of
+// one grid (the table pads every grid to a multiple of spc with empty
+// entries).  That keeps the workgroup count, and the partials the finalize
+// sums, at the one-rhs level.
+
 // r = b - A x, partial ||r||^2
 template <int R, int CF>
 __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const double *__restrict__ val,
@@ -1371,19 +1378,22 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
                                                           const double *__restrict__ b,
                                                           const double *__restrict__ x,
                                                           double *__restrict__ r, const Seg *__restrict__ tab,
-                                                          double *__restrict__ partials) {
+                                                          double *__restrict__ partials, int spc) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const Seg e = tab[blk];
     const int v = threadIdx.x % R, rl = threadIdx.x / R;
     double acc = 0.0;
-    if (rl < e.count) {
-        const int64_t i = e.row0 + rl;
-        double d;
-        const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
-        const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
-        const double ri = b[i * R + v] - s;
-        r[i * R + v] = ri;
-        acc = ri * ri;
+    for (int it = 0; it < (R == 1 ? 1 : spc); ++it) {
+        const Seg e = tab[(int64_t)blk * (R == 1 ? 1 : spc) + it];
+        if (rl < e.count) {
+            const int64_t i = e.row0 + rl;
+            double d;
+            const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+            const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
+            const double ri = b[i * R + v] - s;
+            r[i * R + v] = ri;
+            if constexpr (R == 1) acc = ri * ri;
+            else acc += ri * ri;
+        }
     }
     store_partial<R>(acc, blk, partials);
 }
@@ -1447,19 +1457,24 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
                                                     const int32_t *__restrict__ dbase,
                                                     const double *__restrict__ p, double *__restrict__ q,
                                                     const Seg *__restrict__ tab, double *__restrict__ partials,
-                                                    const int *__restrict__ done) {
+                                                    const int *__restrict__ done, int spc) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const Seg e = tab[blk];
-    if (done && grid_done<R>(done, e.grid)) return;  // done: NULL for one grid
+    const int64_t first = (int64_t)blk * (R == 1 ? 1 : spc);
+    // the entries of a workgroup belong to one grid
+    if (done && grid_done<R>(done, tab[first].grid)) return;  // done: NULL for one grid
     const int v = threadIdx.x % R, rl = threadIdx.x / R;
     double acc = 0.0;
-    if (rl < e.count) {
-        const int64_t i = e.row0 + rl;
-        double d;
-        const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
-        const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
-        q[i * R + v] = s;
-        acc = p[i * R + v] * s;
+    for (int it = 0; it < (R == 1 ? 1 : spc); ++it) {
+        const Seg e = tab[first + it];
+        if (rl < e.count) {
+            const int64_t i = e.row0 + rl;
+            double d;
+            const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+            const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
+            q[i * R + v] = s;
+            if constexpr (R == 1) acc = p[i * R + v] * s;
+            else acc += p[i * R + v] * s;
+        }
     }
     store_partial<R>(acc, blk, partials);
 }
@@ -1502,17 +1517,22 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, co
 //   kRz:   rho = <r,z>; beta = rho/rho_old (0 at the first iteration)
 //   kPq:   alpha = rho/<p,q>, or a breakdown when <p,q> is not finite and > 0
 //   kRr:   record ||r||/||r0|| and test it against tol
+// Threads of a finalize workgroup: with R right-hand sides, kBlock/R threads
+// per system would need R times as many round trips, so R > 1 uses 1024.
+constexpr int fin_block(int R) { return R == 1 ? kBlock : 1024; }
+
 template <int R, int KIND>
-__global__ __launch_bounds__(kBlock) void k_finalize(const int *__restrict__ gb,
-                                                     const double *__restrict__ partials, Scalars sc,
-                                                     double *__restrict__ hist, int hist_cap, double tol) {
-    __shared__ double sh[(kBlock / 64) * R];
+__global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict__ gb,
+                                                           const double *__restrict__ partials, Scalars sc,
+                                                           double *__restrict__ hist, int hist_cap, double tol) {
+    constexpr int FB = fin_block(R);
+    __shared__ double sh[(FB / 64) * R];
     const int g = blockIdx.x;
     if (KIND != kInit && grid_done<R>(sc.done, g)) return;
     const int v = threadIdx.x % R;
     const int b0 = gb[g], b1 = gb[g + 1];
-    // all loads of a thread in one round trip for up to 32 partials per thread
-    constexpr int kStep = kBlock / R, kU = 32;
+    // all loads of a thread in one round trip for up to kU partials per thread
+    constexpr int kStep = FB / R, kU = R == 1 ? 32 : 64;
     double s = 0.0;
     for (int b = b0 + threadIdx.x / R; b < b1; b += kU * kStep) {
         double t[kU];
@@ -1524,7 +1544,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const int *__restrict__ gb,
 #pragma unroll
         for (int u = 0; u < kU; ++u) s += t[u];
     }
-    const double tot = block_sum<R>(s, sh);
+    const double tot = block_sum<R, FB>(s, sh);
     if (threadIdx.x >= R) return;
     const int sys = g * R + threadIdx.x;
     if (KIND == kInit) {
@@ -1567,18 +1587,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const int *__restrict__ gb,
 
 template <int KIND>
 static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hist_cap, hipStream_t s) {
-    MG_DISPATCH_R(P->R, (k_finalize<RR, KIND><<<P->G, kBlock, 0, s>>>(P->red_gb[table], P->sc.partials, P->sc,
+    MG_DISPATCH_R(P->R, (k_finalize<RR, KIND><<<P->G, fin_block(RR), 0, s>>>(P->red_gb[table], P->sc.partials, P->sc,
                                                                      P->hist, hist_cap, tol)));
     return hipGetLastError();
 }
 
-// SpMV-type kernels: one row per thread (table 0); vector kernels: kVecRows
-// rows per thread (table 1).
+// SpMV-type kernels: one row per R threads, spc table entries per workgroup
+// (table 0); vector kernels: kVecRows*kBlock/R rows per workgroup (table 1).
 hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
 #define MG_INITR(CFV)                                                                                  \
     MG_DISPATCH_R(P->R, (k_init_residual<RR, CFV><<<P->n_red[0], kBlock, 0, s>>>(                       \
-                            L.n, L.val64, L.col, L.dcol, L.dbase, P->b, P->x, P->r, P->red_tab[0], P->sc.partials)));
+                            L.n, L.val64, L.col, L.dcol, L.dbase, P->b, P->x, P->r, P->red_tab[0], P->sc.partials, \
+                            P->spc)));
     if (L.cf == 2) { MG_INITR(2) } else if (L.cf == 1) { MG_INITR(1) } else { MG_INITR(0) }
 #undef MG_INITR
     hipError_t e = hipGetLastError();
@@ -1606,7 +1627,7 @@ hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
 #define MG_SPMVPQ(CFV)                                                                                 \
     MG_DISPATCH_R(P->R, (k_spmv_pq<RR, CFV><<<P->n_red[0], kBlock, 0, s>>>(                             \
                             L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials, \
-                            P->G == 1 ? nullptr : P->sc.done)));
+                            P->G == 1 ? nullptr : P->sc.done, P->spc)));
     if (L.cf == 2) { MG_SPMVPQ(2) } else if (L.cf == 1) { MG_SPMVPQ(1) } else { MG_SPMVPQ(0) }
 #undef MG_SPMVPQ
     hipError_t e = hipGetLastError();

@@ -494,20 +494,28 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
     }
 
     // level-0 reduction tables: grid by grid, chunks of kBlock/R rows (one
-    // per thread) and of kVecRows*kBlock/R rows.  The workgroups of the
+    // row per R threads) and of kVecRows*kBlock/R rows.  The workgroups of the
     // one-row table gather from all colours, so its chunks are ordered slab
-    // by slab (the j-th eighth of every colour, then the next eighth): the
-    // contiguous block range an XCD receives is then one spatial slab, whose
-    // gathers stay in that XCD's L2, instead of one colour that needs
-    // neighbours from the whole grid.
+    // by slab (the j-th slab of every colour, then the next): the contiguous
+    // block range an XCD receives is then a run of spatial slabs, whose
+    // gathers stay near that XCD, instead of one colour that needs
+    // neighbours from the whole grid.  With one rhs a slab is an eighth of the
+    // grid, whose 8-byte vector slice fits an XCD's L2.  With R > 1 an entry
+    // holds only kBlock/R rows, so a workgroup takes spc = R consecutive
+    // entries (kBlock rows): as few workgroups, and partials for the finalize
+    // to sum, as with one rhs.  Every grid is padded with empty entries to a
+    // multiple of spc, so that a workgroup stays within one grid.  A point
+    // then carries 8R bytes and a slab is one z-plane of every colour (a
+    // small gain over eighths at 16 right-hand sides).
     {
         const Level &L0 = P->lev[0];
         int64_t max_blocks = 0;
+        P->spc = R == 1 ? 1 : R;
         for (int t = 0; t < 2; ++t) {
             std::vector<Seg> tab;
             std::vector<int> gb(G + 1, 0);
             const int rows = (t == 0 ? 1 : kVecRows) * kBlock / R;
-            const int slabs = t == 0 ? 8 : 1;
+            const int per = t == 0 ? P->spc : 1;  // entries per workgroup
             if (t == 1 && G == 1) {
                 // one grid: the vector kernels take contiguous chunks of the
                 // whole vector and compute them from the block index
@@ -522,8 +530,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
                 }
             }
             for (int g = 0; g < G && !(t == 1 && G == 1); ++g) {
-                gb[g] = (int)tab.size();
+                gb[g] = (int)(tab.size() / per);
                 const LevelGrid &lg = L0.grids[g];
+                const int slabs = t == 1 ? 1 : R == 1 ? 8 : std::max(1, (lg.nz + 1) / 2);
                 for (int j = 0; j < slabs; ++j)
                     for (int k = 0; k < L0.ncol; ++k) {
                         const int64_t nch = (lg.seg_len[k] + rows - 1) / rows;
@@ -537,10 +546,18 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
                             tab.push_back(e);
                         }
                     }
+                while (tab.size() % per) {
+                    Seg e;  // padding: no rows
+                    e.row0 = lg.seg_off[0];
+                    e.count = 0;
+                    e.grid = (int16_t)g;
+                    e.colour = 0;
+                    tab.push_back(e);
+                }
             }
-            gb[G] = (int)tab.size();
-            P->n_red[t] = (int)tab.size();
-            max_blocks = std::max<int64_t>(max_blocks, (int64_t)tab.size());
+            gb[G] = (int)(tab.size() / per);
+            P->n_red[t] = (int)(tab.size() / per);
+            max_blocks = std::max<int64_t>(max_blocks, (int64_t)P->n_red[t]);
             ST_TRY(upload(&P->red_tab[t], tab, s));
             ST_TRY(upload(&P->red_gb[t], gb, s));
         }

@@ -214,7 +214,8 @@ struct mgpcg_problem {
     // writes when fuse_rz is set (one per workgroup of its last update of
     // each colour; colour k's start at rz_off[k]).
     mg::Seg *red_tab[2] = {nullptr, nullptr};
-    int n_red[2] = {0, 0};
+    int n_red[2] = {0, 0};  // workgroups of the kernels that walk table 0 / table 1
+    int spc = 1;            // table-0 entries per workgroup (R > 1: see the table build)
     int *red_gb[3] = {nullptr, nullptr, nullptr};
     bool fuse_rz = false;
     int64_t rz_off[9] = {};

@@ -331,6 +331,40 @@ def test_fp32_vcycle_batched_and_multi_rhs(mg, order):
             np.testing.assert_array_equal(Z[v * n:(v + 1) * n], o.vcycle32(B[v * n:(v + 1) * n]))
 
 
+@pytest.mark.parametrize("levels,dims", [
+    (4, [(16, 16, 16), (24, 16, 32), (8, 16, 8)]),
+    # ragged one-level grids: the SpMV table of a grid is padded with empty
+    # entries up to a whole number of workgroups
+    (1, [(5, 3, 7), (6, 4, 2), (3, 3, 3)]),
+])
+@pytest.mark.parametrize("nrhs", [4, 16])
+def test_batched_multi_rhs(mg, levels, dims, nrhs):
+    # several grids with several right-hand sides each: vectors are packed grid
+    # after grid, and right-hand side after right-hand side within a grid
+    sizes = [a * b * c for a, b, c in dims]
+    blocks = [(g, v, inputs.uniform(300 + 20 * g + v, n)) for g, n in enumerate(sizes) for v in range(nrhs)]
+    B = np.concatenate([blk for _, _, blk in blocks])
+    print(f"batched {dims} levels {levels} x {nrhs} rhs", flush=True)
+    p = mg.Problem(dims, levels=levels, nrhs=nrhs)
+    Z = host(p.vcycle(dev(B)))
+    Y = host(p.spmv(dev(B)))
+    x, h, its, st = p.solve(dev(B), max_iters=200, tol=1e-9)
+    assert st == mg.OK
+    X = host(x)
+    oras = [Oracle(*d, levels=levels) for d in dims]
+    off = 0
+    for g, v, bv in blocks:
+        o, n = oras[g], sizes[g]
+        np.testing.assert_array_equal(Z[off:off + n], o.vcycle(bv))
+        np.testing.assert_array_equal(Y[off:off + n], o.spmv(bv))
+        xo, ho, ito, _ = o.pcg(bv, max_iters=200, tol=1e-9)
+        sys = g * nrhs + v
+        assert its[sys] == ito
+        hist_ok(h[sys, :ito], ho)
+        np.testing.assert_allclose(X[off:off + n], xo, rtol=0, atol=1e-12 * np.abs(xo).max())
+        off += n
+
+
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("nrhs", [2, 16])
 def test_multi_rhs(mg, nrhs, order):
