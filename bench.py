@@ -107,9 +107,20 @@ def dominant_kernel(torch, mg, prob, reps=40):
     r = torch.rand(n, dtype=torch.float64, device="cuda")
     z = torch.rand(n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
-    for _ in range(3):  # warm-up; also puts the host ahead of the device
+    for _ in range(3):  # warm-up
         mg.mgpcg_gs_sweep(prob.h, 0, r, z, layout=mg.INTERNAL, stream=stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # The launches are queued behind a short spin kernel, so that they run
+    # back to back: otherwise a host slower than one launch per ~14 us would
+    # add its gaps to the measured kernel time.  The spin is sized from a
+    # timed 2^20-cycle spin to ~30 ms, far more than the host needs to queue,
+    # and bounded to 1e6..1e8 cycles (at most 1 s even at a 100 MHz counter).
+    e0.record(stream)
+    torch.cuda._sleep(1 << 20)
+    e1.record(stream)
+    e1.synchronize()
+    cycles_per_ms = (1 << 20) / max(e0.elapsed_time(e1), 1e-3)
+    torch.cuda._sleep(int(min(max(30.0 * cycles_per_ms, 1e6), 1e8)))
     e0.record(stream)
     for _ in range(reps):
         for k in range(8):
