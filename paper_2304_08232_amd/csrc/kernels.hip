@@ -94,9 +94,12 @@ constexpr bool word_needed() {
 
 // The column data are loaded first: the gathers need only them (not the
 // values), so they can leave while the value loads are still streaming.
-template <typename T, uint32_t SKIP, bool NT, int CF>
+// VS: the values were staged in LDS by the workgroup; slot s of this row is
+// at vs[s * vstride].
+template <typename T, uint32_t SKIP, bool NT, int CF, bool VS = false>
 __device__ __forceinline__ void load_raw(const T *__restrict__ val, const int32_t *__restrict__ col,
-                                         const int8_t *__restrict__ dcol, int64_t i, RawRow<T, CF> &rw) {
+                                         const int8_t *__restrict__ dcol, int64_t i, RawRow<T, CF> &rw,
+                                         const T *vs = nullptr, int vstride = 0) {
     if constexpr (CF == 2) {
         // every delta is zero: the columns are implied by the bases
 #pragma unroll
@@ -117,7 +120,8 @@ __device__ __forceinline__ void load_raw(const T *__restrict__ val, const int32_
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
         const bool sk = (SKIP >> s) & 1u;
-        rw.a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
+        if constexpr (VS) rw.a[s] = (!sk || s == kCentre) ? vs[s * vstride] : T(0);
+        else rw.a[s] = (!sk || s == kCentre) ? ld<NT>(val + ell_index(s, i)) : T(0);
     }
 }
 
@@ -152,12 +156,13 @@ __device__ __forceinline__ void decode_cols(const RawRow<T, CF> &rw, const SB &s
 // All value and column loads of the row are issued before anything uses
 // them: 27 value loads plus 7 delta words (int8 deltas), 27 columns (int32),
 // or none (implied columns, whose gathers can then leave at once).
-template <typename T, int R, uint32_t SKIP, bool NT, int CF, class SB>
+template <typename T, int R, uint32_t SKIP, bool NT, int CF, class SB, bool VS = false>
 __device__ __forceinline__ void load_slots(const T *__restrict__ val, const int32_t *__restrict__ col,
                                            const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
-                                           T (&a)[kW], int32_t (&c)[kW]) {
+                                           T (&a)[kW], int32_t (&c)[kW], const T *vs = nullptr,
+                                           int vstride = 0) {
     RawRow<T, CF> rw;
-    load_raw<T, SKIP, NT, CF>(val, col, dcol, i, rw);
+    load_raw<T, SKIP, NT, CF, VS>(val, col, dcol, i, rw, vs, vstride);
 #pragma unroll
     for (int s = 0; s < kW; ++s) a[s] = rw.a[s];
     decode_cols<SKIP, CF>(rw, sb, n, i, c);
@@ -182,12 +187,13 @@ __device__ __forceinline__ void gather_slots(const T *x, int v, const T (&a)[kW]
 // the value loads are still streaming.  (Predicting the columns and gathering
 // together with the operator loads, with a check afterwards, was measured
 // slower on the latency-bound levels: ~4.45 against ~4.0 us per level-2 pass.)
-template <typename T, int R, uint32_t SKIP, bool NT, int CF, class SB>
+template <typename T, int R, uint32_t SKIP, bool NT, int CF, class SB, bool VS = false>
 __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb, int64_t n, int64_t i,
-                                         const T *x, int v, T (&a)[kW], T (&xv)[kW]) {
+                                         const T *x, int v, T (&a)[kW], T (&xv)[kW], const T *vs = nullptr,
+                                         int vstride = 0) {
     int32_t c[kW];
-    load_slots<T, R, SKIP, NT, CF>(val, col, dcol, sb, n, i, a, c);
+    load_slots<T, R, SKIP, NT, CF, SB, VS>(val, col, dcol, sb, n, i, a, c, vs, vstride);
     gather_slots<T, R, SKIP>(x, v, a, c, xv);
 }
 
@@ -195,12 +201,12 @@ __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_
 // column order), skipping padding slots (value 0).  Slots whose bit is set in
 // the compile-time SKIP mask are left out entirely (their x is known to be
 // zero); the diagonal value is always loaded and returned in d.
-template <typename T, int R, uint32_t SKIP, bool NT, int CF>
+template <typename T, int R, uint32_t SKIP, bool NT, int CF, bool VS = false>
 __device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *__restrict__ col,
                                      const int8_t *__restrict__ dcol, const int32_t *__restrict__ sb, int64_t n,
-                                     int64_t i, const T *x, int v, T &d) {
+                                     int64_t i, const T *x, int v, T &d, const T *vs = nullptr, int vstride = 0) {
     T a[kW], xv[kW];
-    load_row<T, R, SKIP, NT, CF>(val, col, dcol, sb, n, i, x, v, a, xv);
+    load_row<T, R, SKIP, NT, CF, decltype(sb), VS>(val, col, dcol, sb, n, i, x, v, a, xv, vs, vstride);
     d = a[kCentre];
     T acc = 0;
 #pragma unroll
@@ -209,6 +215,25 @@ __device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *_
         if (!sk && a[s] != T(0)) acc = acc + a[s] * xv[s];
     }
     return acc;
+}
+
+// With R >= kStageR right-hand sides, R lanes share each row: rather than
+// each loading the row's 27 values (R times the address work for the same
+// bytes, which made these kernels bound by address processing), the
+// workgroup stages the values of its `rows` rows (from row0, `count` of them
+// real) in LDS with coalesced loads, slot-major: slot s of row j at
+// sv[s * rows + j].  Slots in SKIP (other than the diagonal) are not loaded,
+// and nothing reads them.  Ends with a workgroup barrier.  With R = 2 the
+// buffer (27 x 128 rows) costs more occupancy than the halved loads save.
+constexpr int kStageR = 4;
+template <typename T, uint32_t SKIP, bool NT, int ROWS, int BS>
+__device__ __forceinline__ void stage_values(const T *__restrict__ val, int64_t row0, int64_t count, T *sv) {
+    for (int e = threadIdx.x; e < kW * ROWS; e += BS) {
+        const int s = e / ROWS, j = e - s * ROWS;
+        const bool need = !((SKIP >> s) & 1u) || s == kCentre;
+        if (need && j < count) sv[e] = ld<NT>(val + ell_index(s, row0 + j));
+    }
+    __syncthreads();
 }
 
 // colour of row i from the colour ranges (at most 8)
@@ -501,12 +526,13 @@ __device__ __forceinline__ void store_partial(double acc, int blk, double *parti
 // the stores wait for it, so a pass does not begin with a round trip.
 // Returns r_i times the stored z_i when DOT (for <r, z>), else 0.
 template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, class SB, bool TWICE = false,
-          bool DOT = false>
+          bool DOT = false, bool VS = false>
 __device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val, const int32_t *__restrict__ col,
                                          const int8_t *__restrict__ dcol, const SB &sb,
                                          const T *__restrict__ r, T *z, int64_t i, int v, int64_t inj_base,
                                          T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
-                                         const int *__restrict__ dflag = nullptr) {
+                                         const int *__restrict__ dflag = nullptr, const T *vs = nullptr,
+                                         int vstride = 0) {
     const int64_t o = i * R + v;
     const int dv = dflag ? *dflag : 0;
     // the transfer map and the coarse value travel with the operator loads
@@ -515,7 +541,7 @@ __device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val,
     int64_t co = 0;
     if (MODE != 0) co = (int64_t)inj_coarse[i - inj_base] * R + v;
     T a[kW], xv[kW];
-    load_row<T, R, SKIP, NT, CF>(val, col, dcol, sb, n, i, z, v, a, xv);
+    load_row<T, R, SKIP, NT, CF, SB, VS>(val, col, dcol, sb, n, i, z, v, a, xv, vs, vstride);
     T zc = T(0);
     if (MODE == 2) zc = coarse[co];
     // z_i before this pass (refined in MODE 2); 0 on a zero start
@@ -576,6 +602,22 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
             rz = pass_row<T, R, SKIP, NT, MODE, CF, Base27, TWICE, true>(
                 n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse, inj_coarse, done ? done + v : nullptr);
         store_partial<R, pass_block(NT)>(rz, b, rzp);
+    } else if constexpr (R >= kStageR) {
+        // R lanes per row: the workgroup's values go through LDS once
+        constexpr int RW = pass_block(NT) / R;
+        __shared__ T sv[kW * RW];
+        if (tab && done) {  // a grid whose systems are all converged: uniform, before the barrier
+            bool all = true;
+#pragma unroll
+            for (int u = 0; u < R; ++u) all = all && done[grid * R + u];
+            if (all) return;
+        }
+        stage_values<T, SKIP, NT, RW, pass_block(NT)>(val, row0, count, sv);
+        if (rl >= count) return;
+        if (tab && done && done[grid * R + v]) return;
+        pass_row<T, R, SKIP, NT, MODE, CF, Base27, TWICE, false, true>(
+            n, val, col, dcol, sb, r, z, row0 + rl, v, row_base, coarse, inj_coarse,
+            tab || !done ? nullptr : done + v, sv + rl, RW);
     } else {
         if (rl >= count) return;
         // several grids: a converged grid is skipped before anything is
@@ -1384,15 +1426,32 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
     double acc = 0.0;
     for (int it = 0; it < (R == 1 ? 1 : spc); ++it) {
         const Seg e = tab[(int64_t)blk * (R == 1 ? 1 : spc) + it];
-        if (rl < e.count) {
-            const int64_t i = e.row0 + rl;
-            double d;
-            const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
-            const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
-            const double ri = b[i * R + v] - s;
-            r[i * R + v] = ri;
-            if constexpr (R == 1) acc = ri * ri;
-            else acc += ri * ri;
+        if constexpr (R < kStageR) {
+            if (rl < e.count) {
+                const int64_t i = e.row0 + rl;
+                double d;
+                const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+                const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
+                const double ri = b[i * R + v] - s;
+                r[i * R + v] = ri;
+                if constexpr (R == 1) acc = ri * ri;
+                else acc += ri * ri;
+            }
+        } else {
+            // R lanes per row: the entry's values go through LDS once
+            __shared__ double sv[kW * (kBlock / R)];
+            stage_values<double, 0u, true, kBlock / R, kBlock>(val, e.row0, e.count, sv);
+            if (rl < e.count) {
+                const int64_t i = e.row0 + rl;
+                double d;
+                const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+                const double s = row_sum<double, R, 0u, true, CF, true>(val, col, dcol, sb, n, i, x, v, d,
+                                                                         sv + rl, kBlock / R);
+                const double ri = b[i * R + v] - s;
+                r[i * R + v] = ri;
+                acc += ri * ri;
+            }
+            __syncthreads();  // the next entry overwrites sv
         }
     }
     store_partial<R>(acc, blk, partials);
@@ -1466,14 +1525,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
     double acc = 0.0;
     for (int it = 0; it < (R == 1 ? 1 : spc); ++it) {
         const Seg e = tab[first + it];
-        if (rl < e.count) {
-            const int64_t i = e.row0 + rl;
-            double d;
-            const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
-            const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
-            q[i * R + v] = s;
-            if constexpr (R == 1) acc = p[i * R + v] * s;
-            else acc += p[i * R + v] * s;
+        if constexpr (R < kStageR) {
+            if (rl < e.count) {
+                const int64_t i = e.row0 + rl;
+                double d;
+                const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+                const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
+                q[i * R + v] = s;
+                if constexpr (R == 1) acc = p[i * R + v] * s;
+                else acc += p[i * R + v] * s;
+            }
+        } else {
+            // R lanes per row: the entry's values go through LDS once
+            __shared__ double sv[kW * (kBlock / R)];
+            stage_values<double, 0u, true, kBlock / R, kBlock>(val, e.row0, e.count, sv);
+            if (rl < e.count) {
+                const int64_t i = e.row0 + rl;
+                double d;
+                const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+                const double s = row_sum<double, R, 0u, true, CF, true>(val, col, dcol, sb, n, i, p, v, d,
+                                                                         sv + rl, kBlock / R);
+                q[i * R + v] = s;
+                acc += p[i * R + v] * s;
+            }
+            __syncthreads();  // the next entry overwrites sv
         }
     }
     store_partial<R>(acc, blk, partials);
@@ -1531,8 +1606,8 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
     if (KIND != kInit && grid_done<R>(sc.done, g)) return;
     const int v = threadIdx.x % R;
     const int b0 = gb[g], b1 = gb[g + 1];
-    // all loads of a thread in one round trip for up to kU partials per thread
-    constexpr int kStep = FB / R, kU = R == 1 ? 32 : 64;
+    // all loads of a thread in one round trip for up to 32 partials per thread
+    constexpr int kStep = FB / R, kU = 32;  // 64 would spill at 1024 threads
     double s = 0.0;
     for (int b = b0 + threadIdx.x / R; b < b1; b += kU * kStep) {
         double t[kU];
