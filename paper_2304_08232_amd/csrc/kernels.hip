@@ -1660,10 +1660,44 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
     }
 }
 
+// One grid with R > 1: the per-workgroup partials of a reduction (nblk * R
+// of them, up to 2M at 16 right-hand sides) are more than one finalize
+// workgroup reads quickly.  kFoldBlocks workgroups first sum fixed,
+// contiguous slices of them, each in a fixed order, into fold[w * R + rhs].
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_fold(const double *__restrict__ partials, int nblk,
+                                                 double *__restrict__ fold) {
+    __shared__ double sh[(kBlock / 64) * R];
+    const int w = blockIdx.x;
+    const int b0 = (int)((int64_t)nblk * w / kFoldBlocks), b1 = (int)((int64_t)nblk * (w + 1) / kFoldBlocks);
+    const int v = threadIdx.x % R;
+    constexpr int kStep = kBlock / R, kU = 8;
+    double s = 0.0;
+    for (int b = b0 + threadIdx.x / R; b < b1; b += kU * kStep) {
+        double t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int bb = b + u * kStep;
+            t[u] = bb < b1 ? partials[(int64_t)bb * R + v] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) s += t[u];
+    }
+    const double tot = block_sum<R>(s, sh);
+    if (threadIdx.x < R) fold[w * R + threadIdx.x] = tot;
+}
+
 template <int KIND>
 static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hist_cap, hipStream_t s) {
-    MG_DISPATCH_R(P->R, (k_finalize<RR, KIND><<<P->G, fin_block(RR), 0, s>>>(P->red_gb[table], P->sc.partials, P->sc,
-                                                                     P->hist, hist_cap, tol)));
+    const int *gb = P->red_gb[table];
+    const double *parts = P->sc.partials;
+    if (P->fold && table < 2) {
+        MG_DISPATCH_R(P->R, (k_fold<RR><<<kFoldBlocks, kBlock, 0, s>>>(P->sc.partials, P->n_red[table], P->fold)));
+        gb = P->fold_gb;
+        parts = P->fold;
+    }
+    MG_DISPATCH_R(P->R, (k_finalize<RR, KIND><<<P->G, fin_block(RR), 0, s>>>(gb, parts, P->sc, P->hist, hist_cap,
+                                                                              tol)));
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ constexpr int kW = 27;        // ELL width (3x3x3 stencil)
 constexpr int kCentre = 13;   // slot of the diagonal
 constexpr int kBlock = 256;   // threads per workgroup
 constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
+constexpr int kFoldBlocks = 64;  // workgroups that pre-sum the CG partials (one grid, R > 1)
 // Workgroup size of a colour pass: 256 threads on streamed (large) levels;
 // one wavefront on cache-resident levels, whose passes are latency-bound, so
 // that their few rows are spread over as many CUs as possible.
@@ -216,6 +217,11 @@ struct mgpcg_problem {
     mg::Seg *red_tab[2] = {nullptr, nullptr};
     int n_red[2] = {0, 0};  // workgroups of the kernels that walk table 0 / table 1
     int spc = 1;            // table-0 entries per workgroup (R > 1: see the table build)
+    // one grid with R > 1: the per-workgroup partials are first summed by
+    // kFoldBlocks workgroups into fold[w * R + rhs], and the finalize reads
+    // those (fold_gb = {0, kFoldBlocks}); NULL otherwise
+    double *fold = nullptr;
+    int *fold_gb = nullptr;
     int *red_gb[3] = {nullptr, nullptr, nullptr};
     bool fuse_rz = false;
     int64_t rz_off[9] = {};
