@@ -366,7 +366,7 @@ def test_batched_multi_rhs(mg, levels, dims, nrhs):
 
 
 @pytest.mark.parametrize("order", [0, 1])
-@pytest.mark.parametrize("nrhs", [2, 16])
+@pytest.mark.parametrize("nrhs", [2, 4, 8, 16])
 def test_multi_rhs(mg, nrhs, order):
     dims = (16, 16, 16)
     o = Oracle(*dims, colour_order=order)
