@@ -306,6 +306,47 @@ def extensions(torch, mg):
             ext["smoother_sweeps"][f"{dims[0]}cubed_{name}"] = row
             log("smoother sweeps:", dims, name, row)
 
+    # differentiable solve, 96^3, theta ~ N(0, 0.5^2): the forward solve, the
+    # adjoint solve with the same matrix and the fused theta-gradient kernel,
+    # to 1e-10 each, and one end-to-end autograd step (which also builds the
+    # problem, since the autograd function creates it from theta)
+    dims = (96, 96, 96)
+    n = dims[0] * dims[1] * dims[2]
+    theta, bd, xt = inputs.differentiable_inputs(5, n)
+    th = torch.tensor(theta, device="cuda")
+    bdt = torch.tensor(bd, device="cuda")
+    xtt = torch.tensor(xt, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pd = mg.Problem(dims, levels=LEVELS, theta=th)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    tf, (xd, _, itf, stf) = time_to_tol(torch, pd, bdt, 1e-10, max_iters=500)
+    ta, (lam, _, ita, sta) = time_to_tol(torch, pd, (xd - xtt).contiguous(), 1e-10, max_iters=500)
+    tg_us = event_us(lambda: pd.theta_grad(lam, xd, th), 10)
+    pd.close()
+    thg, bg = th.clone().requires_grad_(True), bdt.clone().requires_grad_(True)
+
+    def autograd_step():
+        x = mg.MGPCGSolve.apply(thg, bg, dims, LEVELS, 1e-10, 500)
+        (0.5 * ((x - xtt) ** 2).sum()).backward()
+
+    autograd_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    autograd_step()
+    torch.cuda.synchronize()
+    t_step = time.perf_counter() - t0
+    ext["differentiable_96cubed"] = {
+        "setup_s": round(t_setup, 4), "forward_s": round(tf, 5), "forward_iters": int(itf[0]),
+        "adjoint_s": round(ta, 5), "adjoint_iters": int(ita[0]), "theta_grad_us": round(tg_us, 1),
+        "forward_plus_backward_over_forward": round((tf + ta + tg_us * 1e-6) / tf, 3),
+        "autograd_step_s": round(t_step, 4),
+        "converged": bool(stf == mg.OK and sta == mg.OK)}
+    log("differentiable:", ext["differentiable_96cubed"])
+    del th, bdt, xtt, xd, lam, thg, bg
+    torch.cuda.empty_cache()
+
     ext["hpcg_validation"] = hpcg_validation(torch, mg, inputs)
 
     # the autotuner on the benchmark's own problem: 50-iteration solves under
