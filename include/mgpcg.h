@@ -279,8 +279,9 @@ mgpcg_status mgpcg_set_schedule(mgpcg_problem *p, const mgpcg_schedule *sched, h
  * natural layout, or NULL for b = A*1.  cache_path (HOST string, may be
  * NULL): a text file with one JSON object per line; if it holds an entry for
  * this problem (grids, levels, right-hand sides, precision, colour order,
- * smoother, sweeps) on this kind of device, that schedule is applied without
- * timing, otherwise the chosen one is appended.  *chosen (HOST, may be NULL)
+ * smoother, sweeps) on this kind of device, the last such entry is applied
+ * without timing; an entry with fields mgpcg_set_schedule would reject is
+ * ignored.  Otherwise the chosen schedule is appended.  *chosen (HOST, may be NULL)
  * receives the applied schedule.  iters in 1..1000, reps in 1..100.
  * Allocates two vectors of the level-0 size for the duration of the call and
  * synchronises the stream.  The timed runs are solves on this problem: a

@@ -1559,9 +1559,13 @@ mgpcg_status mgpcg_autotune(mgpcg_problem *p, const double *b, int iters, int re
     const std::string key = problem_signature(p);
     mgpcg_schedule S = schedule_of(p);
     if (cache_path && cache_lookup(cache_path, key, &S)) {
-        ST_TRY(apply_schedule(p, S, s));
-        if (chosen) *chosen = schedule_of(p);
-        return MGPCG_OK;
+        // apply_schedule checks every field before it changes anything; an
+        // entry it rejects (an edited file) is ignored and the tuning runs
+        if (apply_schedule(p, S, s) == MGPCG_OK) {
+            if (chosen) *chosen = schedule_of(p);
+            return MGPCG_OK;
+        }
+        S = schedule_of(p);
     }
     // right-hand side and iterate in the internal layout, owned by this call
     Level &L0 = p->lev[0];

@@ -137,6 +137,17 @@ def test_autotune_applies_caches_and_keeps_results(mg, tmp_path):
     r = mg.Problem((16, 16, 16))
     r.autotune(None, iters=5, reps=1, cache_path=cache)
     assert len(open(cache).read().splitlines()) == 3
+    # an entry this build rejects (coarse_mode 7) is ignored: the tuning runs
+    # and appends a valid entry, and the results stay bit-identical
+    bad = dict(entry, coarse_mode=7)
+    with open(cache, "a") as f:
+        f.write(json.dumps(bad) + "\n")
+    u = mg.Problem(dims)
+    tuned = u.autotune(b, iters=5, reps=2, cache_path=cache)
+    assert tuned["coarse_mode"] in (0, 1) and u.schedule == tuned
+    assert len(open(cache).read().splitlines()) == 5
+    x2, h2 = solve(u, b)
+    assert torch.equal(x2, x0) and np.array_equal(h2, h0)
 
 
 def test_autotune_batched_and_sequential(mg):
