@@ -1,8 +1,10 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-  python -m paper_2304_08232_amd.profsummary trace DIR [--cmd "..."]
+  python -m paper_2304_08232_amd.profsummary trace DIR [--cmd "..."] [--match REGEX]
       kernel time per (kernel, grid size) from a --kernel-trace run
-      (rocpd SQLite database or kernel_trace.csv under DIR)
+      (rocpd SQLite database or kernel_trace.csv under DIR); --match keeps
+      the kernels whose short name matches REGEX (e.g. the instantiations for
+      16 right-hand sides)
   python -m paper_2304_08232_amd.profsummary pmc DIR KERNEL_SUBSTR GRID [--cmd "..."]
       mean per-dispatch counter values (FETCH_SIZE / WRITE_SIZE, KiB) of the
       dispatches of one kernel at one grid size, and of the calibration copy
@@ -21,6 +23,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sqlite3
 import sys
 from collections import defaultdict
@@ -47,8 +50,11 @@ def load_trace(d):
     return rows
 
 
-def trace_summary(d, cmd, top=40):
+def trace_summary(d, cmd, top=40, match=None):
     rows = load_trace(d)
+    if match:
+        pat = re.compile(match)
+        rows = [r for r in rows if pat.search(_short(r[0]))]
     agg = defaultdict(lambda: [0, 0.0])
     for name, grid, dur in rows:
         a = agg[(_short(name), grid)]
@@ -170,9 +176,10 @@ def main():
     ap.add_argument("--cmd", default="")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--match", default=None)
     a = ap.parse_args()
     if a.mode == "trace":
-        print(trace_summary(a.dir, a.cmd))
+        print(trace_summary(a.dir, a.cmd, match=a.match))
     elif a.mode == "pmc":
         print(pmc_summary(a.dir, a.args[0], int(a.args[1]), a.cmd))
     elif a.mode == "traffic-all":
