@@ -14,6 +14,20 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/*
+ * Two builds come from this one file.  Without OpenMP it is the canonical
+ * sequential checker.  With -fopenmp (a timing mode only: the CPU baseline
+ * the benchmark reports) the loops over independent rows -- the rows of one
+ * colour, the rows of a product, the elements of a vector update -- are
+ * split statically over the threads, and inner products are summed over
+ * fixed per-thread chunks, so that a run is deterministic for a given
+ * thread count.  Sequential parts (the V-cycle recursion, the sequential
+ * smoother of Eq. (1)) stay sequential.
+ */
 
 /* ------------------------------------------------------------------ utils */
 
@@ -38,6 +52,28 @@ static double logistic(double t) {
  * CG amplifies past a 1e-12 comparison bar, so the terms are accumulated in
  * the x87 extended format (64-bit significand) and rounded once at the end. */
 double ora_dot(int64_t n, const double *a, const double *b) {
+#ifdef _OPENMP
+    /* timing mode: one contiguous chunk per thread, chunk sums added in
+     * thread order */
+    int nt = omp_get_max_threads();
+    if (nt > 1 && n >= 4096) {
+        long double part[256];
+        if (nt > 256) nt = 256;
+#pragma omp parallel num_threads(nt)
+        {
+            int t = omp_get_thread_num(), T = omp_get_num_threads();
+            int64_t lo = n * t / T, hi = n * (t + 1) / T;
+            long double s = 0.0L;
+            for (int64_t i = lo; i < hi; ++i) s += (long double)a[i] * (long double)b[i];
+            part[t] = s;
+            if (t == 0)
+                for (int u = T; u < nt; ++u) part[u] = 0.0L;
+        }
+        long double s = 0.0L;
+        for (int t = 0; t < nt; ++t) s += part[t];
+        return (double)s;
+    }
+#endif
     long double s = 0.0L;
     for (int64_t i = 0; i < n; ++i) s += (long double)a[i] * (long double)b[i];
     return (double)s;
@@ -259,6 +295,7 @@ void ora_get_f2c(const ora_hier *h, int level, int64_t *f2c) {
 /* Sec. II-C: y = A x, each row summed in CRS order. */
 void ora_spmv(const ora_hier *h, int level, const double *x, double *y) {
     const ora_level *L = &h->lev[level];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < L->n; ++i) {
         double s = 0.0;
         for (int64_t e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) s += L->val[e] * x[L->col[e]];
@@ -266,31 +303,39 @@ void ora_spmv(const ora_hier *h, int level, const double *x, double *y) {
     }
 }
 
+/* (A z)_i over the stored row in ascending column order, diagonal included */
+static double row_product(const ora_level *L, int64_t i, const double *z) {
+    double acc = 0.0;
+    for (int64_t e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) acc += L->val[e] * z[L->col[e]];
+    return acc;
+}
+
 /*
- * Sec. III-A, Listings 2 and 3: one colour of the coloured Gauss-Seidel pass.
- * First the masked product s = A z restricted to the rows of colour k (the
- * diagonal term included), then for those rows
- *     z_i <- (r_i - s_i + z_i * d_i) / d_i,
- * which is Eq. (1) with the diagonal term added back.  All s_i are formed
- * from the z values held before the colour's update, as in the listings.
+ * Sec. III-A with Eq. (1): the colour class k of the coloured Gauss-Seidel
+ * smoother.  Each row i of the class solves its own equation of A z = r for
+ * z_i, every other unknown held at its value from before the class is
+ * visited.  Eq. (1) sums the off-diagonal terms; the coloured form of
+ * Sec. III-A sums the whole stored row and puts the diagonal term back,
+ *     z_i <- (r_i - (A z)_i + a_ii z_i) / a_ii,
+ * equal to Eq. (1) in exact arithmetic, and the form whose rounding is
+ * fixed here (left to right, one true division).  The new values of the
+ * class are collected first and stored afterwards, so no row of the class
+ * reads another row's new value (the class has no internal couplings when
+ * the colouring is proper, which the tests pin separately).
  */
 void ora_colour_pass(const ora_hier *h, int level, int k, const double *r, double *z) {
     const ora_level *L = &h->lev[level];
-    int64_t a = L->cstart[k], b = L->cstart[k + 1];
-    double *s = (double *)xcalloc((size_t)(b - a), sizeof(double));
-    for (int64_t t = a; t < b; ++t) {
-        int64_t i = L->clist[t];
-        double acc = 0.0;
-        for (int64_t e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) acc += L->val[e] * z[L->col[e]];
-        s[t - a] = acc;
+    int64_t first = L->cstart[k], count = L->cstart[k + 1] - first;
+    double *znew = (double *)xcalloc((size_t)count, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = L->clist[first + t];
+        double aii = L->diag[i];
+        znew[t] = (r[i] - row_product(L, i, z) + z[i] * aii) / aii;
     }
-    for (int64_t t = a; t < b; ++t) {
-        int64_t i = L->clist[t];
-        double d = L->diag[i];
-        double v = r[i] - s[t - a] + z[i] * d;
-        z[i] = v / d;
-    }
-    free(s);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) z[L->clist[first + t]] = znew[t];
+    free(znew);
 }
 
 /*
@@ -311,6 +356,7 @@ void ora_restrict(const ora_hier *h, int level, const double *r, const double *z
     const ora_level *C = &h->lev[level + 1];
     double *f = (double *)xcalloc((size_t)L->n, sizeof(double));
     ora_spmv(h, level, z, f);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < C->n; ++j) {
         int64_t i = L->f2c[j];
         rc[j] = r[i] - f[i];
@@ -398,6 +444,7 @@ void ora_vcycle_lex(const ora_hier *h, int level, const double *r, double *z) {
 /* The same steps as above in single precision, for the FP32 V-cycle. */
 
 static void spmv32(const ora_level *L, const float *x, float *y) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < L->n; ++i) {
         float s = 0.0f;
         for (int64_t e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) s += L->val32[e] * x[L->col[e]];
@@ -405,22 +452,25 @@ static void spmv32(const ora_level *L, const float *x, float *y) {
     }
 }
 
+static float row_product32(const ora_level *L, int64_t i, const float *z) {
+    float acc = 0.0f;
+    for (int64_t e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) acc += L->val32[e] * z[L->col[e]];
+    return acc;
+}
+
+/* ora_colour_pass in single precision: FP32 values, sums and division */
 static void colour_pass32(const ora_level *L, int k, const float *r, float *z) {
-    int64_t a = L->cstart[k], b = L->cstart[k + 1];
-    float *s = (float *)xcalloc((size_t)(b - a), sizeof(float));
-    for (int64_t t = a; t < b; ++t) {
-        int64_t i = L->clist[t];
-        float acc = 0.0f;
-        for (int64_t e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) acc += L->val32[e] * z[L->col[e]];
-        s[t - a] = acc;
+    int64_t first = L->cstart[k], count = L->cstart[k + 1] - first;
+    float *znew = (float *)xcalloc((size_t)count, sizeof(float));
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = L->clist[first + t];
+        float aii = L->diag32[i];
+        znew[t] = (r[i] - row_product32(L, i, z) + z[i] * aii) / aii;
     }
-    for (int64_t t = a; t < b; ++t) {
-        int64_t i = L->clist[t];
-        float d = L->diag32[i];
-        float v = r[i] - s[t - a] + z[i] * d;
-        z[i] = v / d;
-    }
-    free(s);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) z[L->clist[first + t]] = znew[t];
+    free(znew);
 }
 
 void ora_sgs32(const ora_hier *h, int level, const float *r, float *z) {
@@ -478,6 +528,7 @@ int ora_pcg(const ora_hier *h, const double *b, double *x, int max_iters,
     double *q = (double *)xcalloc((size_t)n, sizeof(double));
     int status = 0, k = 0;
     ora_spmv(h, 0, x, q);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     double nr0 = sqrt(ora_dot(n, r, r));
     double rho_old = 0.0;
@@ -492,6 +543,7 @@ int ora_pcg(const ora_hier *h, const double *b, double *x, int max_iters,
             memcpy(p, z, (size_t)n * sizeof(double));
         } else {
             double beta = rho / rho_old;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         }
         rho_old = rho;
@@ -499,8 +551,11 @@ int ora_pcg(const ora_hier *h, const double *b, double *x, int max_iters,
         double pq = ora_dot(n, p, q);
         if (!(pq > 0.0) || !isfinite(pq)) { status = -5; --k; break; }
         double alpha = rho / pq;
-        for (int64_t i = 0; i < n; ++i) x[i] += alpha * p[i];
-        for (int64_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
         double rel = sqrt(ora_dot(n, r, r)) / nr0;
         if (history) history[k - 1] = rel;
         if (tol > 0.0 && rel <= tol) break;

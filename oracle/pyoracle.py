@@ -11,15 +11,19 @@ import numpy as np
 
 from . import build as _build
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_build.LIB):
+def lib(omp=False):
+    """The sequential oracle (the checker), or with omp=True the OpenMP
+    timing build of the same source.  MGPCG_ORACLE_LIB names another build
+    of the sequential oracle to load instead (the mutation tests use it)."""
+    key = bool(omp)
+    if key not in _libs:
+        path = _build.LIB_OMP if omp else os.environ.get("MGPCG_ORACLE_LIB", _build.LIB)
+        if not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
         L.ora_create.restype = vp
         L.ora_create.argtypes = [i32, i32, i32, i32, i32, vp]
@@ -50,8 +54,8 @@ def lib():
         L.ora_theta_grad.argtypes = [i64, vp, vp, vp, vp]
         L.ora_dot.restype = dbl
         L.ora_dot.argtypes = [i64, vp, vp]
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _p(a):
@@ -66,7 +70,8 @@ def _f64(a):
 class Oracle:
     """One level hierarchy of the MG-PCG problem, built by the C oracle."""
 
-    def __init__(self, nx, ny, nz, levels=4, colour_order=0, theta=None, sweeps=1):
+    def __init__(self, nx, ny, nz, levels=4, colour_order=0, theta=None, sweeps=1, omp=False):
+        self._L = lib(omp)
         self.dims = (nx, ny, nz)
         self.levels = levels
         self.colour_order = colour_order
@@ -74,16 +79,16 @@ class Oracle:
         if theta is not None:
             th = _f64(theta)
             assert th.size == nx * ny * nz
-        self._h = lib().ora_create(nx, ny, nz, levels, colour_order, None if th is None else _p(th))
+        self._h = self._L.ora_create(nx, ny, nz, levels, colour_order, None if th is None else _p(th))
         if not self._h:
             raise ValueError(f"oracle: invalid problem {nx}x{ny}x{nz} levels={levels}")
-        if lib().ora_set_sweeps(self._h, sweeps) != 0:
+        if self._L.ora_set_sweeps(self._h, sweeps) != 0:
             self.close()
             raise ValueError(f"oracle: invalid sweep count {sweeps}")
 
     def close(self):
         if self._h:
-            lib().ora_destroy(self._h)
+            self._L.ora_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -94,13 +99,13 @@ class Oracle:
 
     # --- introspection
     def n(self, level=0):
-        return lib().ora_n(self._h, level)
+        return self._L.ora_n(self._h, level)
 
     def nnz(self, level=0):
-        return lib().ora_nnz(self._h, level)
+        return self._L.ora_nnz(self._h, level)
 
     def ncolours(self, level=0):
-        return lib().ora_ncolours(self._h, level)
+        return self._L.ora_ncolours(self._h, level)
 
     def level_dims(self, level):
         return tuple(d >> level for d in self.dims)
@@ -110,7 +115,7 @@ class Oracle:
         rp = np.zeros(n + 1, np.int64)
         col = np.zeros(nnz, np.int32)
         val = np.zeros(nnz, np.float64)
-        lib().ora_get_crs(self._h, level, _p(rp), _p(col), _p(val))
+        self._L.ora_get_crs(self._h, level, _p(rp), _p(col), _p(val))
         return rp, col, val
 
     def dense(self, level=0):
@@ -123,74 +128,74 @@ class Oracle:
 
     def colours(self, level=0):
         c = np.zeros(self.n(level), np.int32)
-        lib().ora_get_colours(self._h, level, _p(c))
+        self._L.ora_get_colours(self._h, level, _p(c))
         return c
 
     def f2c(self, level=0):
         m = np.zeros(self.n(level + 1), np.int64)
-        lib().ora_get_f2c(self._h, level, _p(m))
+        self._L.ora_get_f2c(self._h, level, _p(m))
         return m
 
     # --- building blocks
     def spmv(self, x, level=0):
         x = _f64(x)
         y = np.zeros(self.n(level))
-        lib().ora_spmv(self._h, level, _p(x), _p(y))
+        self._L.ora_spmv(self._h, level, _p(x), _p(y))
         return y
 
     def colour_pass(self, k, r, z, level=0):
         r = _f64(r)
         z = _f64(z).copy()
-        lib().ora_colour_pass(self._h, level, k, _p(r), _p(z))
+        self._L.ora_colour_pass(self._h, level, k, _p(r), _p(z))
         return z
 
     def sgs(self, r, z, level=0):
         r = _f64(r)
         z = _f64(z).copy()
-        lib().ora_sgs(self._h, level, _p(r), _p(z))
+        self._L.ora_sgs(self._h, level, _p(r), _p(z))
         return z
 
     def sgs32(self, r, z, level=0):
         r = np.ascontiguousarray(r, dtype=np.float32)
         z = np.ascontiguousarray(z, dtype=np.float32).copy()
-        lib().ora_sgs32(self._h, level, _p(r), _p(z))
+        self._L.ora_sgs32(self._h, level, _p(r), _p(z))
         return z
 
     def restrict(self, r, z, level=0):
         r, z = _f64(r), _f64(z)
         rc = np.zeros(self.n(level + 1))
-        lib().ora_restrict(self._h, level, _p(r), _p(z), _p(rc))
+        self._L.ora_restrict(self._h, level, _p(r), _p(z), _p(rc))
         return rc
 
     def prolong_add(self, zc, z, level=0):
         zc = _f64(zc)
         z = _f64(z).copy()
-        lib().ora_prolong_add(self._h, level, _p(zc), _p(z))
+        self._L.ora_prolong_add(self._h, level, _p(zc), _p(z))
         return z
 
     def vcycle(self, r, level=0):
         r = _f64(r)
         z = np.zeros(self.n(level))
-        lib().ora_vcycle(self._h, level, _p(r), _p(z))
+        self._L.ora_vcycle(self._h, level, _p(r), _p(z))
         return z
 
     def sgs_lex(self, r, z, level=0):
         """Sequential symmetric Gauss-Seidel (Eq. (1), natural row order)."""
         r = _f64(r)
         z = _f64(z).copy()
-        lib().ora_sgs_lex(self._h, level, _p(r), _p(z))
+        self._L.ora_sgs_lex(self._h, level, _p(r), _p(z))
         return z
 
     def vcycle_lex(self, r, level=0):
         r = _f64(r)
         z = np.zeros(self.n(level))
-        lib().ora_vcycle_lex(self._h, level, _p(r), _p(z))
+        self._L.ora_vcycle_lex(self._h, level, _p(r), _p(z))
         return z
 
     def vcycle32(self, r):
         r = _f64(r)
         z = np.zeros(self.n(0))
-        lib().ora_vcycle32(self._h, _p(r), _p(z))
+        self._L.ora_vcycle32(self._h, _p(r), _p(z))
         return z
 
     def pcg(self, b, x0=None, max_iters=50, tol=0.0, precond=1):
@@ -199,7 +204,7 @@ class Oracle:
         x = np.zeros(self.n(0)) if x0 is None else _f64(x0).copy()
         hist = np.zeros(max(max_iters, 1))
         it = C.c_int(0)
-        st = lib().ora_pcg(self._h, _p(b), _p(x), max_iters, float(tol), precond,
+        st = self._L.ora_pcg(self._h, _p(b), _p(x), max_iters, float(tol), precond,
                            _p(hist), C.byref(it))
         return x, hist[: it.value].copy(), it.value, st
 

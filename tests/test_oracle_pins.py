@@ -472,6 +472,118 @@ def test_fp32_vcycle_close_to_fp64():
     np.testing.assert_allclose(zz, ref, rtol=1e-5, atol=1e-7)
 
 
+# The V-cycle is held bit for bit by the GPU tests (FP64 and FP32), so its
+# arithmetic is pinned bit for bit here: against a brute force that visits
+# rows one at a time (sequential Gauss-Seidel in colour-stable order, which
+# equals the coloured pass because no two rows of a colour are coupled),
+# reads the rows of a dense matrix, and rounds every operation to the working
+# precision (numpy scalars of that type).  The update is the coloured form of
+# Sec. III-A, the whole-row sum with the diagonal term put back (reading D6).
+# A mistake that widens a step of the FP32 path (a double accumulator, a
+# double residual, FP64 operator values), or that uses another form of the
+# update, moves last bits and fails these.
+
+def _bf_rows(A, dt):
+    """Nonzero columns (ascending) and values, rounded to dt, of each dense row."""
+    Ad = A.astype(dt)
+    rows = []
+    for i in range(Ad.shape[0]):
+        cols = np.nonzero(Ad[i])[0]
+        rows.append((cols, Ad[i, cols]))
+    return rows, np.diag(Ad).copy()
+
+
+def _bf_row_dot(cols, vals, z):
+    dt = z.dtype.type
+    acc = dt(0.0)
+    for j, a in zip(cols, vals):
+        acc = dt(acc + dt(a * z[j]))
+    return acc
+
+
+def _bf_gs_visit(rows, d, r, z, order):
+    dt = z.dtype.type
+    z = z.copy()
+    for i in order:
+        cols, vals = rows[i]
+        s = _bf_row_dot(cols, vals, z)
+        z[i] = dt(dt(dt(r[i] - s) + dt(z[i] * d[i])) / d[i])
+    return z
+
+
+def _bf_sgs(rows, d, colour, r, z):
+    fwd = bf.colour_sorted_order(colour)
+    return _bf_gs_visit(rows, d, r, _bf_gs_visit(rows, d, r, z, fwd), fwd[::-1])
+
+
+def _bf_vcycle(hier, r, l=0):
+    rows, d, colour, inj = hier[l]
+    z = _bf_sgs(rows, d, colour, r, np.zeros_like(r))
+    if l == len(hier) - 1:
+        return z
+    f = np.array([_bf_row_dot(c, v, z) for c, v in rows], dtype=r.dtype)
+    rc = (r - f)[inj]
+    zc = _bf_vcycle(hier, rc, l + 1)
+    z = z.copy()
+    z[inj] = z[inj] + zc
+    return _bf_sgs(rows, d, colour, r, z)
+
+
+def _bf_hierarchy(o, dt):
+    hier = []
+    for l in range(o.levels):
+        rows, d = _bf_rows(o.dense(l), dt)
+        inj = bf.injection_matrix(*o.level_dims(l)).argmax(axis=1) if l + 1 < o.levels else None
+        hier.append((rows, d, o.colours(l), inj))
+    return hier
+
+
+@pytest.mark.parametrize("dims,theta", [((4, 4, 4), False), ((6, 5, 4), False), ((4, 4, 4), True)])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_sweep_bitexact_scalar_bruteforce(dims, theta, order, dt):
+    rng = np.random.default_rng(60)
+    n = dims[0] * dims[1] * dims[2]
+    th = rng.normal(0, 0.5, n) if theta else None
+    o = Oracle(*dims, levels=1, colour_order=order, theta=th)
+    rows, d = _bf_rows(o.dense(), dt)
+    r = rng.uniform(-1, 1, n).astype(dt)
+    z0 = rng.uniform(-1, 1, n).astype(dt)
+    ref = _bf_sgs(rows, d, o.colours(), r, z0)
+    assert ref.dtype == dt
+    if dt == np.float32:
+        np.testing.assert_array_equal(o.sgs32(r, z0), ref)
+        # genuinely single precision: the FP64 sweep differs
+        assert not np.array_equal(o.sgs(r.astype(np.float64), z0.astype(np.float64)), ref.astype(np.float64))
+    else:
+        np.testing.assert_array_equal(o.sgs(r, z0), ref)
+
+
+@pytest.mark.parametrize("dims,levels", [((4, 4, 4), 3), ((8, 8, 8), 4), ((8, 4, 4), 3)])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_vcycle_bitexact_scalar_bruteforce(dims, levels, order, dt):
+    rng = np.random.default_rng(61)
+    o = Oracle(*dims, levels=levels, colour_order=order)
+    hier = _bf_hierarchy(o, dt)
+    for _ in range(2):
+        r = rng.uniform(-1, 1, o.n())
+        ref = _bf_vcycle(hier, r.astype(dt))  # FP32: r rounded to nearest at entry
+        got = o.vcycle32(r) if dt == np.float32 else o.vcycle(r)
+        np.testing.assert_array_equal(got, ref.astype(np.float64))
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_vcycle_bitexact_with_theta(dt):
+    rng = np.random.default_rng(62)
+    th = rng.normal(0, 0.5, 64)
+    o = Oracle(4, 4, 4, levels=3, theta=th)
+    r = rng.uniform(-1, 1, 64)
+    ref = _bf_vcycle(_bf_hierarchy(o, dt), r.astype(dt))
+    got = o.vcycle32(r) if dt == np.float32 else o.vcycle(r)
+    np.testing.assert_array_equal(got, ref.astype(np.float64))
+
+
 def test_fp32_pcg_reaches_tolerance():
     o = Oracle(16, 16, 16, levels=4)
     b = o.spmv(np.ones(o.n()))
@@ -479,6 +591,70 @@ def test_fp32_pcg_reaches_tolerance():
     _, h32, it32, st = o.pcg(b, max_iters=100, tol=1e-9, precond=2)
     assert st == 0 and h32[-1] <= 1e-9
     assert abs(it32 - it64) <= 2
+
+
+# ---------------------------------------------------- inner product (Sec. II-C)
+#
+# Reading taken for the inner products of CG: their value is the exact sum
+# of the products, which the oracle approaches by accumulating in the x87
+# extended format (64-bit significand) and rounding once.  These pin that
+# claim against exact arithmetic, on inputs where a plain left-to-right
+# double sum fails.
+
+def test_dot_exact_on_integer_cancellation():
+    # integers of at most 26 bits: every product is exact in double, and with
+    # every partial sum below 2^63 (checked below with exact integers) every
+    # partial sum is exact in a 64-bit significand, so the result must be the
+    # exact sum rounded once.  Terms cancel in shuffled pairs, and the
+    # partial sums reach far past 2^53, where double addition rounds.
+    import math
+    rng = np.random.default_rng(70)
+    m = 3000
+    a1 = rng.integers(1 << 22, 1 << 26, m) * rng.choice([-1, 1], m)
+    b1 = rng.integers(1 << 22, 1 << 26, m)
+    a = np.concatenate([a1, -a1])
+    b = np.concatenate([b1, b1 + rng.integers(-3, 4, m)])
+    perm = rng.permutation(2 * m)
+    a, b = a[perm], b[perm]
+    prods = [int(x) * int(y) for x, y in zip(a, b)]
+    partial, exact = 0, 0
+    for t in prods:
+        exact += t
+        partial = max(partial, abs(exact))
+    assert partial < 2 ** 63 and partial > 2 ** 56
+    af, bf_ = a.astype(np.float64), b.astype(np.float64)
+    assert math.fsum(af * bf_) == float(exact)  # products exact, fsum correctly rounded
+    assert Oracle.dot(af, bf_) == float(exact)
+    naive = 0.0
+    for x, y in zip(af, bf_):
+        naive += x * y
+    assert naive != float(exact)  # a plain double sum gets it wrong
+
+
+def test_dot_two_million_terms_against_fsum():
+    # the size of the 128^3 problem's vectors; the reference is the correctly
+    # rounded exact dot product: each product split exactly into its rounded
+    # value and its error (Dekker's product with Veltkamp splitting), then
+    # summed by math.fsum
+    import math
+    rng = np.random.default_rng(71)
+    n = 1 << 21
+    a, b = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+
+    def split(x):
+        c = 134217729.0 * x  # 2^27 + 1
+        hi = c - (c - x)
+        return hi, x - hi
+
+    p = a * b
+    ah, al = split(a)
+    bh, bl = split(b)
+    e = ((ah * bh - p) + ah * bl + al * bh) + al * bl
+    ref = math.fsum(np.concatenate([p, e]))
+    got = Oracle.dot(a, b)
+    naive = float(np.cumsum(p)[-1])  # left to right in double
+    assert abs(got - ref) <= 2.0 ** -52 * abs(ref)
+    assert abs(naive - ref) > 16 * 2.0 ** -52 * abs(ref)
 
 
 # ------------------------------------------------------- differentiable solve
