@@ -5,9 +5,9 @@ whole V-cycle) are compared bit for bit: the library disables FP contraction
 and sums each row in the oracle's order, so the same IEEE operations happen
 on both sides.  CG adds reductions whose summation order differs (tree on the
 GPU, sequential in the oracle), so residual histories are compared with the
-rule in parity.py: 1e-12 relative while the relative residual is >= 1e-6
-(every entry of the 128^3 run), looser below, where the residual is made of
-rounding noise.
+rule in parity.py: 1e-12 relative plus a noise floor, in units of the
+initial residual, that matters only where the residual is made of rounding
+noise.
 """
 import json
 import os
@@ -433,12 +433,37 @@ def test_128cubed_pcg_history_golden(mg, p128):
     x, h, its, st = p128.solve(b, max_iters=50)
     assert st == mg.OK and its[0] == 50
     ho = np.array(gold["history"])
-    assert ho.min() >= 1e-6  # the whole history is in the strict 1e-12 regime
+    assert ho.min() >= 1e-6  # far above the noise floor: the rule is 1e-12 relative here
     np.testing.assert_allclose(h[0], ho, rtol=1e-12, atol=0)
     xg = host(x)
     idx = np.array(gold["sample_index"])
     np.testing.assert_allclose(xg[idx], np.array(gold["sample_x"]), rtol=1e-12, atol=0)
     assert abs(np.abs(xg - 1.0).max() - gold["max_abs_err"]) <= 1e-12
+
+
+def test_128cubed_order1_streamed_levels(mg):
+    # colour order 1 at full size: level 0 (453 MB of FP64 operator) runs the
+    # 256-thread non-temporal builds with the order-1 zero-start masks and the
+    # unfused restriction and refinement; the coarse levels do real work
+    dims = (128, 128, 128)
+    print("128^3 order 1", flush=True)
+    o = Oracle(*dims, colour_order=1)
+    p = mg.Problem(dims, levels=4, colour_order=1)
+    assert p.schedule["wide_levels"] & 1
+    r = inputs.uniform(80, o.n())
+    np.testing.assert_array_equal(host(p.vcycle(dev(r))), o.vcycle(r))
+    for l in range(4):
+        n = o.n(l)
+        x, z0 = inputs.uniform(81 + l, n), inputs.uniform(85 + l, n)
+        np.testing.assert_array_equal(host(p.gs_sweep(dev(x), dev(z0), level=l)), o.sgs(x, z0, level=l))
+        if l < 3:
+            np.testing.assert_array_equal(host(p.restrict(dev(x), dev(z0), level=l)), o.restrict(x, z0, level=l))
+    b = o.spmv(np.ones(o.n()))
+    xo, ho, ito, _ = o.pcg(b, max_iters=20)
+    x, h, its, st = p.solve(dev(b), max_iters=20)
+    assert st == mg.OK and its[0] == 20
+    hist_ok(h[0], ho)
+    np.testing.assert_allclose(host(x), xo, rtol=0, atol=1e-12 * np.abs(xo).max())
 
 
 # ------------------------------------------- coarse levels: persistent kernel

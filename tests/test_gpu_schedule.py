@@ -75,6 +75,38 @@ def test_every_schedule_bit_identical(mg, case):
     p.check()
 
 
+def test_every_schedule_order1_matches_oracle(mg):
+    # Colour order 1 cannot fuse the transfers into the passes, so its levels
+    # run the unfused restriction and refinement kernels, and a level whose
+    # wide_levels bit is set runs the 256-thread, non-temporal builds with the
+    # order-1 zero-start masks (by default only levels above 128 MiB, i.e. at
+    # 128^3 and up).  Every schedule is compared with the oracle: the V-cycle
+    # bit for bit, the CG history by the history rule (changing bit 0 regroups
+    # the fused <r,z> partials, so solves are not bit-identical across it).
+    dims = (32, 32, 32)
+    o = Oracle(*dims, colour_order=1)
+    p = mg.Problem(dims, levels=4, colour_order=1)
+    print("schedules order 1", flush=True)
+    r = inputs.uniform(12, o.n())
+    z_ref = o.vcycle(r)
+    b = inputs.uniform(7, o.n())
+    xo, ho, ito, _ = o.pcg(b, max_iters=12)
+    base = {}
+    for c in candidates(4, False):
+        p.set_schedule(**c)
+        assert p.schedule == c
+        np.testing.assert_array_equal(p.vcycle(dev(r)).cpu().numpy(), z_ref, err_msg=str(c))
+        x, h = solve(p, dev(b))
+        assert_history_close(h[0], ho)
+        # within one setting of bit 0 every other choice is bit-identical
+        key = c["wide_levels"] & 1
+        if key in base:
+            assert torch.equal(x, base[key][0]) and np.array_equal(h, base[key][1]), c
+        else:
+            base[key] = (x, h)
+    p.check()
+
+
 def test_level0_width_on_fused_problem_matches_oracle(mg):
     dims = (32, 32, 32)
     o = Oracle(*dims)
