@@ -189,6 +189,22 @@ mgpcg_status mgpcg_prolong_add(const mgpcg_problem *p, int level, const double *
 mgpcg_status mgpcg_mg_vcycle(const mgpcg_problem *p, const double *r, double *z, int layout,
                              hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the V-cycle
+ * of mgpcg_mg_vcycle, same arguments and the same results bit for bit, with
+ * no device allocation and no hipMalloc/hipFree in the call.  (mgpcg_mg_vcycle
+ * allocates per-level staging buffers on its first call.)  The natural-layout
+ * staging of r and z goes through a fixed 32 MiB array that the library holds
+ * on every device it runs on until the process ends: in natural layout at
+ * most 2^21 level-0 values (n*R) are accepted, larger problems return
+ * MGPCG_ERR_INVALID_ARG before anything is launched (MGPCG_LAYOUT_INTERNAL has
+ * no limit; it stages nothing).  Every call on one device shares that array,
+ * and the handle's own level vectors as mgpcg_mg_vcycle does: calls that
+ * overlap on one device (other streams, other handles) race and must be
+ * ordered by the caller. */
+mgpcg_status mgpcg_mg_vcycle_noalloc(const mgpcg_problem *p, const double *r, double *z, int layout,
+                                     hipStream_t stream);
+
 /* Sec. II-C: preconditioned CG for all S systems at once, starting from x
  * (x holds x0 on entry and the iterate on exit).  Per system: r = b - A x,
  * then per iteration z = M r, rho = <r,z>, p = z + (rho/rho_old) p (p = z at

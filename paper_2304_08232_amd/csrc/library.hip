@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1163,6 +1164,35 @@ mgpcg_status time_schedule(mgpcg_problem *P, const mgpcg_schedule &S, const doub
 
 }  // namespace
 
+// ----------------------------------- staging of the no-allocation entry point
+//
+// mgpcg_mg_vcycle_noalloc permutes natural-layout vectors through this array
+// instead of buffers it would allocate: r in its first half, z in its second.
+// One copy per device, held by the code object until the process ends.  In
+// host code the symbol is not a device address: kernels get the address that
+// hipGetSymbolAddress returns on each device (kept in g_scratch by device).
+constexpr int64_t kScratchDoubles = int64_t(1) << 22;  // 32 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch;  // by device; NULL until looked up
+
+// the device address of `scratch` on device `dev`, which must be current
+mgpcg_status scratch_on_device(int dev, double **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = (double *)ptr;
+    }
+    *out = g_scratch[dev];
+    return MGPCG_OK;
+}
+}  // namespace
+
 // ====================================================================== C ABI
 
 extern "C" {
@@ -1212,6 +1242,12 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
         return fail(MGPCG_ERR_NO_DEVICE, "hipGetDevice failed");
+    }
+    // set-up of the no-allocation entry point on this device (once per device)
+    double *scr = nullptr;
+    if (mgpcg_status sst = scratch_on_device(P->device, &scr); sst != MGPCG_OK) {
+        delete P;
+        return sst;
     }
     P->G = cfg->ngrids;
     P->R = R;
@@ -1421,6 +1457,45 @@ mgpcg_status mgpcg_mg_vcycle(const mgpcg_problem *p_, const double *r, double *z
         if (p->mg_dtype == MGPCG_FP64) return vcycle<double>(p, (const double *)rv, (double *)zv, nullptr, s);
         return vcycle<float>(p, (const float *)rv, (float *)zv, nullptr, s);
     });
+}
+
+mgpcg_status mgpcg_mg_vcycle_noalloc(const mgpcg_problem *p_, const double *r, double *z, int layout,
+                                     hipStream_t s) {
+    ST_TRY(check_problem(p_));
+    ST_TRY(check_layout(layout));
+    if (!r || !z) return fail(MGPCG_ERR_INVALID_ARG, "NULL vector");
+    mgpcg_problem *p = const_cast<mgpcg_problem *>(p_);
+    const int64_t n = p->lev[0].n * p->R;
+    const bool natural = layout == MGPCG_LAYOUT_NATURAL;
+    if (natural && 2 * n > kScratchDoubles)
+        return fail(MGPCG_ERR_INVALID_ARG, "mgpcg_mg_vcycle_noalloc: " + std::to_string(n) +
+                                               " level-0 values exceed the staging limit of " +
+                                               std::to_string(kScratchDoubles / 2) +
+                                               " in natural layout (use MGPCG_LAYOUT_INTERNAL)");
+    DeviceGuard dg(p->device);
+    double *scr = nullptr;
+    ST_TRY(scratch_on_device(p->device, &scr));
+    ST_TRY(reset_coarse(p, s));
+    const double *ri = r;
+    double *zi = z;
+    if (natural) {
+        HIP_TRY(launch_permute(p, 0, r, scr, true, s));
+        ri = scr;
+        zi = scr + n;
+    }
+    if (p->smoother == MGPCG_SMOOTHER_SEQUENTIAL) {
+        HIP_TRY(vcycle_lex(p, ri, zi, s));
+    } else if (p->mg_dtype == MGPCG_FP64) {
+        HIP_TRY(vcycle<double>(p, ri, zi, nullptr, s));
+    } else {
+        // the FP32 V-cycle runs in the handle's own level-0 vectors
+        Level &L0 = p->lev[0];
+        HIP_TRY(launch_cast_d2f(ri, (float *)L0.r, n, s));
+        HIP_TRY(vcycle<float>(p, (const float *)L0.r, (float *)L0.z, nullptr, s));
+        HIP_TRY(launch_cast_f2d((const float *)L0.z, zi, n, s));
+    }
+    if (natural) HIP_TRY(launch_permute(p, 0, zi, z, false, s));
+    return MGPCG_OK;
 }
 
 mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int max_iters, double rel_tol,

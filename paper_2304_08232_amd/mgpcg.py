@@ -26,7 +26,7 @@ ABI_FUNCTIONS = [
     "mgpcg_create", "mgpcg_destroy", "mgpcg_info", "mgpcg_set_theta", "mgpcg_to_internal",
     "mgpcg_to_natural", "mgpcg_spmv", "mgpcg_make_rhs_ones", "mgpcg_gs_sweep", "mgpcg_colour_pass",
     "mgpcg_restrict",
-    "mgpcg_prolong_add", "mgpcg_mg_vcycle", "mgpcg_pcg_solve", "mgpcg_solve_result",
+    "mgpcg_prolong_add", "mgpcg_mg_vcycle", "mgpcg_mg_vcycle_noalloc", "mgpcg_pcg_solve", "mgpcg_solve_result",
     "mgpcg_theta_grad", "mgpcg_set_graph_mode", "mgpcg_set_coarse_mode", "mgpcg_get_schedule",
     "mgpcg_set_schedule", "mgpcg_autotune", "mgpcg_check", "mgpcg_last_error",
 ]
@@ -82,6 +82,7 @@ def lib():
         L.mgpcg_restrict.argtypes = [vp, i32, vp, vp, vp, i32, vp]
         L.mgpcg_prolong_add.argtypes = [vp, i32, vp, vp, i32, vp]
         L.mgpcg_mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
+        L.mgpcg_mg_vcycle_noalloc.argtypes = [vp, vp, vp, i32, vp]
         L.mgpcg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, vp, vp, i32, vp]
         L.mgpcg_solve_result.argtypes = [vp, i32, vp, vp, vp]
         L.mgpcg_theta_grad.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -179,6 +180,10 @@ def mgpcg_prolong_add(h, level, zc, z, layout=NATURAL, stream=None):
 
 def mgpcg_mg_vcycle(h, r, z, layout=NATURAL, stream=None):
     return _check(lib().mgpcg_mg_vcycle(C.c_void_p(h), _ptr(r), _ptr(z), layout, _stream(stream)))
+
+
+def mgpcg_mg_vcycle_noalloc(h, r, z, layout=NATURAL, stream=None):
+    return _check(lib().mgpcg_mg_vcycle_noalloc(C.c_void_p(h), _ptr(r), _ptr(z), layout, _stream(stream)))
 
 
 def mgpcg_pcg_solve(h, b, x, max_iters, rel_tol=0.0, history=None, iters=None, layout=NATURAL,
