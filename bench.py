@@ -59,6 +59,49 @@ def measured_traffic(per_launch_alg_bytes):
     return d.get("hbm_bytes_per_launch")
 
 
+def counted_iteration_traffic():
+    """HBM bytes of one 128^3 CG iteration from the committed counter summary,
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "iteration_128cubed_traffic.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2304_08232_amd.profsummary import kernel_source_hash
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_iteration")
+
+
+def stream_read_ceiling(torch, gib=4, reps=5):
+    """GB/s of a plain streaming-read kernel (libceiling.so, 16-byte
+    non-temporal loads) over a `gib` GiB buffer: the best of `reps` timed
+    reads at each of a few grid sizes."""
+    import ctypes as C
+    from paper_2304_08232_amd import build as libbuild
+    L = C.CDLL(libbuild.CEILING_LIB)
+    L.ceiling_stream_read.restype = C.c_int
+    L.ceiling_stream_read.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p]
+    nbytes = gib << 30
+    buf = torch.zeros(nbytes // 8, dtype=torch.float64, device="cuda")
+    out = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    best = 0.0
+    for blocks in (1024, 2048, 4096, 8192):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for rep in range(reps + 1):
+            e0.record(stream)
+            rc = L.ceiling_stream_read(C.c_void_p(buf.data_ptr()), nbytes // 16, C.c_void_p(out.data_ptr()), blocks,
+                                       C.c_void_p(stream.cuda_stream))
+            e1.record(stream)
+            e1.synchronize()
+            if rc != 0:
+                raise RuntimeError(f"ceiling_stream_read failed: {rc}")
+            if rep:
+                best = max(best, nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del buf, out
+    return best
+
+
 def time_solves(torch, mg, prob, b, x, steps, warmup, iters):
     """Mean wall time per step over `steps` solves, and the standard deviation
     of the per-step times taken from HIP events recorded between the steps on
@@ -131,18 +174,41 @@ def dominant_kernel(torch, mg, prob, reps=40):
     return e0.elapsed_time(e1) * 1e-3 / launches, launches
 
 
-def cpu_baseline(iters=25):
+def cpu_baseline(reps=10):
+    """The C oracle timed on this host, in its two builds: OpenMP on the
+    host's cores (rows of a colour, of a product and of a vector update split
+    statically over the threads; inner products over fixed per-thread
+    chunks), and the sequential checker.  Each: one warm-up solve, then
+    `reps` timed solves of a few iterations of the 128^3 FP64 problem (b =
+    A*1, x0 = 0, set-up untimed); the mean and standard deviation of the
+    rate by the nominal model.  `value` is the OpenMP build's mean."""
     from oracle import Oracle
     from paper_2304_08232_amd import perfmodel
-    o = Oracle(*GRID, levels=LEVELS)
-    b = o.spmv(np.ones(o.n()))
-    t0 = time.perf_counter()
-    x, h, it, st = o.pcg(b, max_iters=iters)
-    t = time.perf_counter() - t0
     _, F = perfmodel.iteration([GRID], LEVELS, "fp64")
-    return {"value": round(F * iters / t / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} MG-PCG iterations of the 128^3 FP64 problem (setup untimed), "
-                      f"single-threaded C oracle, {t:.1f} s"}
+    host_cores = len(os.sched_getaffinity(0))
+    out = {}
+    for mode, omp, iters in (("openmp", True, 6), ("single_thread", False, 2)):
+        o = Oracle(*GRID, levels=LEVELS, omp=omp)
+        b = o.spmv(np.ones(o.n()))
+        o.pcg(b, max_iters=1)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            o.pcg(b, max_iters=iters)
+            ts.append(time.perf_counter() - t0)
+        rates = [F * iters / t / 1e9 for t in ts]
+        out[mode] = {"gflops_mean": round(float(np.mean(rates)), 4), "gflops_std": round(float(np.std(rates, ddof=1)), 4),
+                     "threads": int(o.threads()), "iterations_per_rep": iters, "reps": reps,
+                     "s_per_iteration": round(float(np.mean(ts)) / iters, 4)}
+        o.close()
+        log(f"cpu baseline {mode}: {out[mode]}")
+    om = out["openmp"]
+    return {"value": om["gflops_mean"], "unit": "GFLOP/s", "cores": om["threads"], "kind": "oracle",
+            "std": om["gflops_std"], "host_cores": host_cores, "modes": out,
+            "sample": f"{reps} solves of {om['iterations_per_rep']} MG-PCG iterations of the 128^3 FP64 problem "
+                      f"(b = A*1, x0 = 0, set-up untimed) by the OpenMP build of the C oracle on "
+                      f"{om['threads']} threads; the sequential build ({reps} x "
+                      f"{out['single_thread']['iterations_per_rep']} iterations) under modes"}
 
 
 def extensions(torch, mg):
@@ -491,10 +557,15 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 5 * 2 * src.numel() * 8 / (time.perf_counter() - t0) / 1e9
     del src, dst
+    read_gbs = stream_read_ceiling(torch)
+    log(f"streaming-read ceiling: {read_gbs:.1f} GB/s")
     B, F = perfmodel.iteration([GRID], LEVELS, "fp64")
     gflops = F * ITERS / time_to_solve / 1e9
     hbm_frac = B * ITERS / time_to_solve / (perfmodel.HBM_PEAK_GBS * 1e9)
     achieved = per_launch_bytes / t_launch / 1e9
+    traffic = measured_traffic(per_launch_bytes)
+    it_bytes = counted_iteration_traffic()
+    us_it = t_step / ITERS * 1e6
     line = {
         "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 4),
@@ -505,14 +576,22 @@ def main():
                    "coarse_mode": args.coarse_mode,
                    "iterations_per_step": ITERS, "colour_order": 0, "rhs": "A*ones", "x0": "zeros",
                    "layout": "internal (resident in HBM)"},
+        # nominal: the method's bytes (12 B per nonzero with int32 columns);
+        # measured: the HBM bytes the counters saw, from the committed summary
         "nominal_hbm_frac": round(hbm_frac, 4),
-        "us_per_iteration": round(t_step / ITERS * 1e6, 2),
+        "measured_hbm_bytes_per_iteration": it_bytes,
+        "measured_hbm_frac": None if it_bytes is None else round(it_bytes / (us_it * 1e-6) / 8e12, 4),
+        "us_per_iteration": round(us_it, 2),
         "final_relres": float(hist[-1]),
         "stream_copy_gbs": round(copy_gbs, 1),
+        "stream_read_gbs": round(read_gbs, 1),
         "roofline": {"bound": "hbm", "kernel": "k_pass<double, 1, 0u, true, 0, 2, false, false> (level-0 colour pass)",
                      "achieved": round(achieved, 1), "peak": perfmodel.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / perfmodel.HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(per_launch_bytes),
+                     "traffic": traffic,
+                     "achieved_counted": None if traffic is None else round(traffic / t_launch / 1e9, 1),
+                     "frac_counted": None if traffic is None else round(traffic / t_launch / 1e9 / perfmodel.HBM_PEAK_GBS, 4),
+                     "frac_of_read_ceiling_counted": None if traffic is None else round(traffic / t_launch / 1e9 / read_gbs, 4),
                      "alg_bytes_per_launch": int(per_launch_bytes),
                      "avg_launch_us": round(t_launch * 1e6, 3)},
     }

@@ -79,6 +79,15 @@ double ora_dot(int64_t n, const double *a, const double *b) {
     return (double)s;
 }
 
+/* threads the loops of this build run on (1 for the sequential checker) */
+int ora_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ---------------------------------------------------- problem generation */
 
 /*

@@ -103,6 +103,10 @@ int ora_pcg(const ora_hier *h, const double *b, double *x, int max_iters,
 void ora_theta_grad(int64_t n, const double *lambda, const double *x,
                     const double *theta, double *grad);
 
+/* Threads the loops of this build use: 1 for the sequential checker, the
+ * OpenMP thread count for the timing build (-fopenmp). */
+int ora_threads(void);
+
 /* Inner product used by CG: sequential, extended-precision accumulator. */
 double ora_dot(int64_t n, const double *a, const double *b);
 

@@ -54,6 +54,8 @@ def lib(omp=False):
         L.ora_theta_grad.argtypes = [i64, vp, vp, vp, vp]
         L.ora_dot.restype = dbl
         L.ora_dot.argtypes = [i64, vp, vp]
+        L.ora_threads.restype = i32
+        L.ora_threads.argtypes = []
         _libs[key] = L
     return _libs[key]
 
@@ -207,6 +209,10 @@ class Oracle:
         st = self._L.ora_pcg(self._h, _p(b), _p(x), max_iters, float(tol), precond,
                            _p(hist), C.byref(it))
         return x, hist[: it.value].copy(), it.value, st
+
+    def threads(self):
+        """Threads this build's loops run on (1: the sequential checker)."""
+        return self._L.ora_threads()
 
     @staticmethod
     def theta_grad(lam, x, theta):
