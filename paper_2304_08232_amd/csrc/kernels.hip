@@ -19,7 +19,7 @@ namespace mg {
 
 namespace {
 
-constexpr int kXcd = 8;  // XCDs per MI355X; workgroups are dealt round-robin
+constexpr int kXcd = kXcdCount;  // XCDs per MI355X; workgroups are dealt round-robin
 
 // Workgroup b of nb is dispatched to XCD b % 8.  Return the logical block so
 // that each XCD receives one contiguous range of logical blocks.
@@ -226,12 +226,25 @@ __device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *_
 // and nothing reads them.  Ends with a workgroup barrier.  With R = 2 the
 // buffer (27 x 128 rows) costs more occupancy than the halved loads save.
 constexpr int kStageR = 4;
+// A thread's share (at most N = ceil(27 ROWS / BS) words) is loaded into
+// registers first and written to LDS afterwards, so that all its loads are in
+// flight together; words of rows past `count` and of skipped slots are
+// written as 0 and never read.
 template <typename T, uint32_t SKIP, bool NT, int ROWS, int BS>
 __device__ __forceinline__ void stage_values(const T *__restrict__ val, int64_t row0, int64_t count, T *sv) {
-    for (int e = threadIdx.x; e < kW * ROWS; e += BS) {
+    constexpr int N = (kW * ROWS + BS - 1) / BS;
+    T w[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        const int e = threadIdx.x + u * BS;
         const int s = e / ROWS, j = e - s * ROWS;
-        const bool need = !((SKIP >> s) & 1u) || s == kCentre;
-        if (need && j < count) sv[e] = ld<NT>(val + ell_index(s, row0 + j));
+        const bool need = e < kW * ROWS && (!((SKIP >> (s & 31)) & 1u) || s == kCentre) && j < count;
+        w[u] = need ? ld<NT>(val + ell_index(s, row0 + j)) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        const int e = threadIdx.x + u * BS;
+        if (e < kW * ROWS) sv[e] = w[u];
     }
     __syncthreads();
 }
@@ -1509,6 +1522,12 @@ __global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ 
 }
 
 // q = A p, partial <p, q>
+// With one rhs every value load and gather of the row is issued before the
+// sum uses any of them (136 instead of 68 VGPRs, 3 instead of 7 waves per
+// SIMD): the product's 8192 workgroups take several dispatch rounds at any
+// occupancy, and more loads in flight per wave took it from 100 to 92 us at
+// 128^3.  (The colour passes, whose 1024 workgroups fit in one round at the
+// higher occupancy, and the LDS-staged R >= 4 product became slower.)
 template <int R, int CF>
 __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__restrict__ val,
                                                     const int32_t *__restrict__ col,
@@ -1530,7 +1549,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
                 const int64_t i = e.row0 + rl;
                 double d;
                 const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
-                const double s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
+                double s;
+                if constexpr (R == 1) {
+                    double a[kW], xv[kW];
+                    load_row<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, a, xv);
+                    __builtin_amdgcn_sched_barrier(0);  // all loads issued before the sum
+                    s = 0.0;
+#pragma unroll
+                    for (int t = 0; t < kW; ++t)
+                        if (a[t] != 0.0) s = s + a[t] * xv[t];
+                } else {
+                    s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
+                }
                 q[i * R + v] = s;
                 if constexpr (R == 1) acc = p[i * R + v] * s;
                 else acc += p[i * R + v] * s;

@@ -708,7 +708,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
                      need <= (64 << 10) && fits && (G == 1 || Lt.cf == 0);
         P->tail_lw = P->tail_ok ? L - 1 : L;
     }
-    HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int) * mgpcg_problem::kCheckRing, hipHostMallocDefault));
+    for (int j = 0; j < mgpcg_problem::kCheckRing; ++j)
+        HIP_TRY(hipEventCreateWithFlags(&P->check_ev[j], hipEventDisableTiming));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     return MGPCG_OK;
@@ -744,6 +746,8 @@ void free_problem(mgpcg_problem *P) {
     dfree(P->coarse_flags);
     dfree(P->coarse_err);
     if (P->pinned_ndone) (void)hipHostFree(P->pinned_ndone);
+    for (auto &ev : P->check_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (P->iter_graph) (void)hipGraphExecDestroy(P->iter_graph);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     (void)hipSetDevice(cur);
@@ -1556,16 +1560,40 @@ mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int m
             return hip_fail(ie, "hipGraphInstantiate");
         }
     }
+    // Tolerance checks: the count of finished systems is posted after every
+    // iteration (every 4th on small problems, whose iterations are short) and
+    // read once a later iteration is queued behind it, so the host never
+    // drains the stream.  Iterations queued after the last system finished
+    // change nothing (converged systems store nothing), they only cost time:
+    // at most check_every + 1 of them.
     const bool check = rel_tol > 0.0;
     const int check_every = p->lev[0].n * p->R >= (1 << 20) ? 1 : 4;
-    for (int it = 0; it < max_iters; ++it) {
-        if (check && it > 0 && it % check_every == 0) {
-            HIP_TRY(hipMemcpyAsync(p->pinned_ndone, sc.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (*p->pinned_ndone >= S) break;
+    constexpr int kRing = mgpcg_problem::kCheckRing;
+    int posted[kRing];  // iteration after which each outstanding slot was posted
+    int head = 0, tail = 0;
+    bool finished = false;
+    for (int it = 0; it < max_iters && !finished; ++it) {
+        // read every posted count that has an iteration queued behind it
+        // (and the oldest one when the ring is full)
+        while (check && tail > head && (posted[head % kRing] <= it - 2 || tail - head == kRing)) {
+            const int j = head % kRing;
+            HIP_TRY(hipEventSynchronize(p->check_ev[j]));
+            ++head;
+            if (p->pinned_ndone[j] >= S) {
+                finished = true;
+                break;
+            }
         }
+        if (finished) break;
         if (p->iter_graph) HIP_TRY(hipGraphLaunch(p->iter_graph, s));
         else HIP_TRY(cg_iteration(p, rel_tol, s));
+        if (check && (it + 1) % check_every == 0 && it + 1 < max_iters) {
+            const int j = tail % kRing;
+            HIP_TRY(hipMemcpyAsync(p->pinned_ndone + j, sc.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipEventRecord(p->check_ev[j], s));
+            posted[j] = it;
+            ++tail;
+        }
     }
     ST_TRY(out_vec(p, 0, p->x, x, layout, s));
     if (!history_host && !iters_host && rel_tol == 0.0) return MGPCG_OK;

@@ -31,6 +31,7 @@ constexpr int kCentre = 13;   // slot of the diagonal
 constexpr int kBlock = 256;   // threads per workgroup
 constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
 constexpr int kFoldBlocks = 64;  // workgroups that pre-sum the CG partials (one grid, R > 1)
+constexpr int kXcdCount = 8;     // XCDs of the part; workgroup b is dispatched to XCD b % 8
 // Workgroup size of a colour pass: 256 threads on streamed (large) levels;
 // one wavefront on cache-resident levels, whose passes are latency-bound, so
 // that their few rows are spread over as many CUs as possible.
@@ -234,7 +235,13 @@ struct mgpcg_problem {
     int last_max_iters = 0;
     double last_tol = 0.0;
 
-    int *pinned_ndone = nullptr;  // host-pinned mirror for convergence checks
+    // Convergence checks of tolerance-driven solves: after an iteration the
+    // count of finished systems is copied into a host-pinned slot and an
+    // event recorded; the host reads a slot only once a later iteration is
+    // queued behind it, so the device never waits for the host.
+    static constexpr int kCheckRing = 4;
+    int *pinned_ndone = nullptr;  // kCheckRing slots
+    hipEvent_t check_ev[kCheckRing] = {};
 
     // persistent coarse-level V-cycle (levels coarse_lc..L-1 in one launch)
     bool coarse_ok = false;   // supported for this problem
