@@ -252,7 +252,8 @@ def extensions(torch, mg):
     off = 0
     for d, n in zip(dims_list, sizes):
         ps = mg.Problem(d, levels=LEVELS)
-        ts, (xs, hs, its_, sts) = time_to_tol(torch, ps, bb[off:off + n].contiguous(), 1e-9, reps=1)
+        # best of 3, as the batched solve (one warm-up each)
+        ts, (xs, hs, its_, sts) = time_to_tol(torch, ps, bb[off:off + n].contiguous(), 1e-9, reps=3)
         tsum += ts
         its_single.append(int(its_[0]))
         off += n
@@ -279,7 +280,7 @@ def extensions(torch, mg):
     tsum = 0.0
     its_single = []
     for v in range(16):
-        ts, (_, _, its_, _) = time_to_tol(torch, ps, B[v * n:(v + 1) * n].contiguous(), 1e-9, reps=1)
+        ts, (_, _, its_, _) = time_to_tol(torch, ps, B[v * n:(v + 1) * n].contiguous(), 1e-9, reps=3)
         tsum += ts
         its_single.append(int(its_[0]))
     ps.close()
