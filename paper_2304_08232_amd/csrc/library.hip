@@ -502,16 +502,20 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
     // gathers stay near that XCD, instead of one colour that needs
     // neighbours from the whole grid.  With one rhs a slab is an eighth of the
     // grid, whose 8-byte vector slice fits an XCD's L2.  With R > 1 an entry
-    // holds only kBlock/R rows, so a workgroup takes spc = R consecutive
-    // entries (kBlock rows): as few workgroups, and partials for the finalize
-    // to sum, as with one rhs.  Every grid is padded with empty entries to a
-    // multiple of spc, so that a workgroup stays within one grid.  A point
-    // then carries 8R bytes and a slab is one z-plane of every colour (a
-    // small gain over eighths at 16 right-hand sides).
+    // holds only kBlock/R rows and a point carries 8R bytes, so the rows an
+    // XCD has in flight must be a compact region for their gathers to fit
+    // its 4 MB L2: a workgroup takes spc = 2 consecutive entries, and the
+    // entries run half-plane by half-plane (hz), within one by blocks of 8
+    // half-lines (hy), every colour of a block in turn.  At 16 right-hand
+    // sides on 128^3 this took the product's HBM reads from 2.26 GB to
+    // 1.00 GB (about its 0.99 GB of operator, p and q), with 2 x 16 rows
+    // per workgroup instead of 16 x 16 (a z-plane of every colour in turn
+    // read 2.26 GB).  Every grid is padded with empty entries to a multiple
+    // of spc, so that a workgroup stays within one grid.
     {
         const Level &L0 = P->lev[0];
         int64_t max_blocks = 0;
-        P->spc = R == 1 ? 1 : R;
+        P->spc = R == 1 ? 1 : 2;
         for (int t = 0; t < 2; ++t) {
             std::vector<Seg> tab;
             std::vector<int> gb(G + 1, 0);
@@ -533,7 +537,40 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             for (int g = 0; g < G && !(t == 1 && G == 1); ++g) {
                 gb[g] = (int)(tab.size() / per);
                 const LevelGrid &lg = L0.grids[g];
-                const int slabs = t == 1 ? 1 : R == 1 ? 8 : std::max(1, (lg.nz + 1) / 2);
+                if (t == 0 && R > 1) {
+                    // half-plane by half-plane; within one, blocks of kYBlock
+                    // half-lines, every colour of a block in turn
+                    constexpr int64_t kYBlock = 8;
+                    Colouring C(lg.nx, lg.ny, lg.nz, P->colour_order);
+                    int64_t hx[8] = {}, hy[8] = {}, hz[8] = {};
+                    int64_t hzmax = 0, hymax = 0;
+                    for (int k = 0; k < lg.ncol; ++k) {
+                        int b[3];
+                        C.parity(k, b);
+                        hx[k] = half_count(lg.nx, b[0]);
+                        hy[k] = half_count(lg.ny, b[1]);
+                        hz[k] = half_count(lg.nz, b[2]);
+                        hzmax = std::max(hzmax, hz[k]);
+                        hymax = std::max(hymax, hy[k]);
+                    }
+                    for (int64_t jz = 0; jz < hzmax; ++jz)
+                        for (int64_t y0 = 0; y0 < hymax; y0 += kYBlock)
+                            for (int k = 0; k < lg.ncol; ++k) {
+                                if (jz >= hz[k] || y0 >= hy[k]) continue;
+                                const int64_t y1 = std::min<int64_t>(y0 + kYBlock, hy[k]);
+                                const int64_t a0 = lg.seg_off[k] + (jz * hy[k] + y0) * hx[k];
+                                const int64_t a1 = lg.seg_off[k] + (jz * hy[k] + y1) * hx[k];
+                                for (int64_t a = a0; a < a1; a += rows) {
+                                    Seg e;
+                                    e.row0 = a;
+                                    e.count = (int32_t)std::min<int64_t>(rows, a1 - a);
+                                    e.grid = (int16_t)g;
+                                    e.colour = (int16_t)k;
+                                    tab.push_back(e);
+                                }
+                            }
+                }
+                const int slabs = t == 1 ? 1 : R == 1 ? 8 : 0;
                 for (int j = 0; j < slabs; ++j)
                     for (int k = 0; k < L0.ncol; ++k) {
                         const int64_t nch = (lg.seg_len[k] + rows - 1) / rows;
