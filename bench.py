@@ -23,7 +23,7 @@ Also reported on the same line:
                 beside them, and the autotuner's pick for the 128^3 problem.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extensions]
-       [--no-cpu-baseline] [--only-kernel]
+       [--no-cpu-baseline] [--only-kernel] [--only-multi-rhs]
 """
 import argparse
 import json
@@ -497,6 +497,15 @@ def hpcg_validation(torch, mg, inputs, dims=(128, 128, 128), ref_iters=50, sets=
     return out
 
 
+def calibration_copy(torch):
+    """Calibration for the HBM counters: one device copy of exactly 512 MiB."""
+    src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -508,6 +517,8 @@ def main():
                     help="0: one kernel per coarse colour pass; 1: persistent coarse V-cycle")
     ap.add_argument("--only-kernel", action="store_true",
                     help="time only the dominant kernel (for counter runs)")
+    ap.add_argument("--only-multi-rhs", action="store_true",
+                    help="3 eager iterations of the 16-rhs 128^3 solve and a 512 MiB copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is a "
@@ -519,6 +530,15 @@ def main():
     from paper_2304_08232_amd import perfmodel
 
     torch.cuda.set_device(0)
+    if args.only_multi_rhs:
+        from paper_2304_08232_amd import inputs
+        n = GRID[0] * GRID[1] * GRID[2]
+        pm = mg.Problem(GRID, levels=LEVELS, nrhs=16)
+        pm.set_graph_mode(False)
+        pm.solve(torch.tensor(inputs.multi_rhs(41, 16, n), device="cuda"), max_iters=3)
+        torch.cuda.synchronize()
+        calibration_copy(torch)
+        return
     prob = mg.Problem(GRID, levels=LEVELS)
     prob.set_coarse_mode(args.coarse_mode)
     log(f"setup done: n={prob.n(0)} nnz={prob.nnz(0)}")
@@ -530,12 +550,7 @@ def main():
         prob.set_graph_mode(False)
         prob.solve(prob.make_rhs_ones(layout=mg.INTERNAL), max_iters=3, layout=mg.INTERNAL)
         torch.cuda.synchronize()
-        # calibration for the HBM counters: one copy of exactly 512 MiB
-        src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        calibration_copy(torch)
         return
 
     b = prob.make_rhs_ones(layout=mg.INTERNAL)
