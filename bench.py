@@ -9,8 +9,13 @@ library's internal layout.  value = nominal GFLOP/s of the method as written
 Also reported on the same line:
   roofline      the dominant kernel (one colour pass of the level-0 sweep),
                 algorithmic bytes per launch / average launch time from HIP
-                events on the stream it runs on, against 8 TB/s;
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample;
+                events on the stream it runs on, against 8 TB/s; the counted
+                bytes (committed rocprofv3 summary) against 8 TB/s and
+                against the streaming-read ceiling; and the time one launch
+                of a streaming-read kernel over the same bytes takes;
+  cpu_baseline  the CPU oracle on a bounded sample: its OpenMP build on the
+                host's cores (value) and its sequential build, 10 timed
+                repetitions each;
   extensions    FP32-V-cycle vs FP64 to 1e-9 at 192^3, 64 batched uneven
                 grids and 16 right-hand sides vs one-at-a-time solves, both
                 colour numberings to 1e-9 at 64^3 and 128^3, the
@@ -575,6 +580,13 @@ def main():
     del src, dst
     read_gbs = stream_read_ceiling(torch)
     log(f"streaming-read ceiling: {read_gbs:.1f} GB/s")
+    # the floor for a kernel of the dominant pass's size: one launch of the
+    # streaming-read kernel over the bytes the pass moves (counted when the
+    # committed counter summary matches the sources, else its model bytes)
+    from paper_2304_08232_amd import floors
+    pass_bytes = measured_traffic(per_launch_bytes) or per_launch_bytes
+    one_shot_us = floors.one_shot_read_us(torch, int(pass_bytes))
+    log(f"one streaming read of {pass_bytes / 1e6:.1f} MB: {one_shot_us:.2f} us")
     B, F = perfmodel.iteration([GRID], LEVELS, "fp64")
     gflops = F * ITERS / time_to_solve / 1e9
     hbm_frac = B * ITERS / time_to_solve / (perfmodel.HBM_PEAK_GBS * 1e9)
@@ -608,6 +620,8 @@ def main():
                      "achieved_counted": None if traffic is None else round(traffic / t_launch / 1e9, 1),
                      "frac_counted": None if traffic is None else round(traffic / t_launch / 1e9 / perfmodel.HBM_PEAK_GBS, 4),
                      "frac_of_read_ceiling_counted": None if traffic is None else round(traffic / t_launch / 1e9 / read_gbs, 4),
+                     "one_shot_read_us": round(one_shot_us, 3),
+                     "frac_of_one_shot_read": round(one_shot_us / (t_launch * 1e6), 4),
                      "alg_bytes_per_launch": int(per_launch_bytes),
                      "avg_launch_us": round(t_launch * 1e6, 3)},
     }
