@@ -621,6 +621,8 @@ def main():
                      "frac_counted": None if traffic is None else round(traffic / t_launch / 1e9 / perfmodel.HBM_PEAK_GBS, 4),
                      "frac_of_read_ceiling_counted": None if traffic is None else round(traffic / t_launch / 1e9 / read_gbs, 4),
                      "one_shot_read_us": round(one_shot_us, 3),
+                     "one_shot_read_bytes": int(pass_bytes),
+                     "one_shot_read_bytes_kind": "counted" if traffic is not None else "model",
                      "frac_of_one_shot_read": round(one_shot_us / (t_launch * 1e6), 4),
                      "alg_bytes_per_launch": int(per_launch_bytes),
                      "avg_launch_us": round(t_launch * 1e6, 3)},

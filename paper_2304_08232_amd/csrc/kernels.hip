@@ -1627,44 +1627,67 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, co
 constexpr int fin_block(int R) { return R == 1 ? kBlock : 1024; }
 
 template <int R, int KIND>
-__global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict__ gb,
+__global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict__ gb, int nblk,
                                                            const double *__restrict__ partials, Scalars sc,
                                                            double *__restrict__ hist, int hist_cap, double tol) {
     constexpr int FB = fin_block(R);
     __shared__ double sh[(FB / 64) * R];
     const int g = blockIdx.x;
-    if (KIND != kInit && grid_done<R>(sc.done, g)) return;
     const int v = threadIdx.x % R;
-    const int b0 = gb[g], b1 = gb[g + 1];
-    // all loads of a thread in one round trip for up to 32 partials per thread
+    // One grid (gb == NULL): the partials are [0, nblk), so their loads wait
+    // for no table load.  The convergence flags and the scalars of the
+    // update are loaded after the partials are on their way, so that both
+    // take one memory round trip.  A thread's loads are straight-line (a
+    // load past the end rereads the last partial and adds 0 instead), up to
+    // 32 of them per round trip.
+    const int b0 = gb ? gb[g] : 0, b1 = gb ? gb[g + 1] : nblk;
     constexpr int kStep = FB / R, kU = 32;  // 64 would spill at 1024 threads
-    double s = 0.0;
-    for (int b = b0 + threadIdx.x / R; b < b1; b += kU * kStep) {
-        double t[kU];
+    double t[kU];
+    int b = b0 + threadIdx.x / R;
+    if (b1 > b0) {
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int bb = b + u * kStep;
-            t[u] = bb < b1 ? partials[(int64_t)bb * R + v] : 0.0;
+            t[u] = partials[(int64_t)(bb < b1 ? bb : b1 - 1) * R + v];
         }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) s += t[u];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    const bool gdone = KIND != kInit && grid_done<R>(sc.done, g);
+    const int sys = g * R + (threadIdx.x < R ? threadIdx.x : 0);
+    const int dn = sc.done[sys];
+    const int it0 = (KIND == kRz || KIND == kRr) ? sc.iter[sys] : 0;
+    const double rho_old = KIND == kRz ? sc.rho_old[sys] : 0.0;
+    const double rho = KIND == kPq ? sc.rho[sys] : 0.0;
+    const double nr0 = KIND == kRr ? sc.nr0[sys] : 0.0;
+    double s = 0.0;
+    while (b < b1) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) s += (b + u * kStep < b1) ? t[u] : 0.0;
+        b += kU * kStep;
+        if (b < b1) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int bb = b + u * kStep;
+                t[u] = partials[(int64_t)(bb < b1 ? bb : b1 - 1) * R + v];
+            }
+        }
+    }
+    if (gdone) return;  // uniform over the workgroup
     const double tot = block_sum<R, FB>(s, sh);
     if (threadIdx.x >= R) return;
-    const int sys = g * R + threadIdx.x;
     if (KIND == kInit) {
-        const double nr0 = sqrt(tot);
-        sc.nr0[sys] = nr0;
-        if (nr0 == 0.0) {
+        const double n0 = sqrt(tot);
+        sc.nr0[sys] = n0;
+        if (n0 == 0.0) {
             sc.done[sys] = 1;
             sc.status[sys] = 1;
             atomicAdd(sc.ndone, 1);
         }
         return;
     }
-    if (sc.done[sys]) return;
+    if (dn) return;
     if (KIND == kRz) {
-        sc.beta[sys] = (sc.iter[sys] == 0) ? 0.0 : tot / sc.rho_old[sys];
+        sc.beta[sys] = (it0 == 0) ? 0.0 : tot / rho_old;
         sc.rho[sys] = tot;
         sc.rho_old[sys] = tot;
     } else if (KIND == kPq) {
@@ -1675,12 +1698,12 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
             sc.done[sys] = 1;
             atomicAdd(sc.ndone, 1);
         } else {
-            sc.alpha[sys] = sc.rho[sys] / tot;
+            sc.alpha[sys] = rho / tot;
         }
     } else {
-        const int k = sc.iter[sys] + 1;
+        const int k = it0 + 1;
         sc.iter[sys] = k;
-        const double rel = sqrt(tot) / sc.nr0[sys];
+        const double rel = sqrt(tot) / nr0;
         if (k <= hist_cap) hist[(int64_t)sys * hist_cap + (k - 1)] = rel;
         if (tol > 0.0 && rel <= tol) {
             sc.done[sys] = 1;
@@ -1721,13 +1744,16 @@ template <int KIND>
 static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hist_cap, hipStream_t s) {
     const int *gb = P->red_gb[table];
     const double *parts = P->sc.partials;
+    // partials of one grid: the workgroups of the producing kernel(s)
+    int nblk = table == 2 ? (int)P->rz_off[8] : P->n_red[table];
     if (P->fold && table < 2) {
         MG_DISPATCH_R(P->R, (k_fold<RR><<<kFoldBlocks, kBlock, 0, s>>>(P->sc.partials, P->n_red[table], P->fold)));
-        gb = P->fold_gb;
         parts = P->fold;
+        nblk = kFoldBlocks;
     }
-    MG_DISPATCH_R(P->R, (k_finalize<RR, KIND><<<P->G, fin_block(RR), 0, s>>>(gb, parts, P->sc, P->hist, hist_cap,
-                                                                              tol)));
+    if (P->G == 1) gb = nullptr;  // the range [0, nblk) travels as an argument
+    MG_DISPATCH_R(P->R, (k_finalize<RR, KIND><<<P->G, fin_block(RR), 0, s>>>(gb, nblk, parts, P->sc, P->hist,
+                                                                              hist_cap, tol)));
     return hipGetLastError();
 }
 

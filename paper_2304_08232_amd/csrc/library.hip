@@ -638,8 +638,6 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(dalloc(&sc.partials, max_blocks * R));
         if (G == 1 && R > 1) {
             ST_TRY(dalloc(&P->fold, (int64_t)kFoldBlocks * R));
-            std::vector<int> fgb = {0, kFoldBlocks};
-            ST_TRY(upload(&P->fold_gb, fgb, s));
         }
     }
     // persistent coarse-level V-cycle (levels 1..L-1 in one launch) and the
@@ -778,7 +776,7 @@ void free_problem(mgpcg_problem *P) {
     dfree(sc.rho); dfree(sc.rho_old); dfree(sc.alpha); dfree(sc.beta); dfree(sc.nr0); dfree(sc.pq);
     dfree(sc.iter); dfree(sc.done); dfree(sc.status); dfree(sc.ndone);
     dfree(sc.partials);
-    dfree(P->fold); dfree(P->fold_gb);
+    dfree(P->fold);
     dfree(P->hist);
     dfree(P->coarse_flags);
     dfree(P->coarse_err);

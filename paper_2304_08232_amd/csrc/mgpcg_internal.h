@@ -220,9 +220,8 @@ struct mgpcg_problem {
     int spc = 1;            // table-0 entries per workgroup (R > 1: see the table build)
     // one grid with R > 1: the per-workgroup partials are first summed by
     // kFoldBlocks workgroups into fold[w * R + rhs], and the finalize reads
-    // those (fold_gb = {0, kFoldBlocks}); NULL otherwise
+    // those; NULL otherwise
     double *fold = nullptr;
-    int *fold_gb = nullptr;
     int *red_gb[3] = {nullptr, nullptr, nullptr};
     bool fuse_rz = false;
     int64_t rz_off[9] = {};
