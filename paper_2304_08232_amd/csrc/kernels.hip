@@ -743,6 +743,13 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     const int R = P->R;
     if (rzp && (sizeof(T) != 8 || P->G != 1 || (mode != kPassPlain && mode != kPassTwice)))
         return hipErrorInvalidValue;
+    // With one grid the passes store regardless of convergence: the flag
+    // would put a dependent load in front of every pass (the compiler moves
+    // the test ahead of the loads, whose results are dead when it fails),
+    // and z is internal: after convergence the CG updates leave x, r and p
+    // alone and the finalizes leave the scalars alone.  With several grids
+    // a converged grid's workgroups return before loading anything.
+    if (P->G == 1) done = nullptr;
     // several grids: the kernels read each segment's bases from the device table
     const int32_t *gb = P->G > 1 ? L.dbase : nullptr;
     const Seg *tab = nullptr;
@@ -1492,6 +1499,30 @@ __global__ __launch_bounds__(kBlock) void k_dot_rz(const double *__restrict__ r,
     store_partial<R>(acc, blk, partials);
 }
 
+// The vector kernels' loads of one thread: its kVecRows rows (a row past the
+// chunk's end is read as its last row, and not stored).  The values are
+// consumed by an empty asm statement that runs on every path, so that the
+// compiler cannot move the loads behind a test of the convergence flag:
+// otherwise, the loads being dead when the flag is set, it tests the flag
+// first, and every kernel begins with a dependent load of it.
+template <int R, int N>
+__device__ __forceinline__ void vec_rows(const Seg &e, int v, int64_t (&o)[kVecRows], const double *(&src)[N],
+                                         double (&val)[N][kVecRows]) {
+#pragma unroll
+    for (int u = 0; u < kVecRows; ++u) {
+        const int rl = threadIdx.x / R + u * (kBlock / R);
+        o[u] = (e.row0 + (rl < e.count ? rl : e.count - 1)) * R + v;
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int u = 0; u < kVecRows; ++u) val[a][u] = src[a][o[u]];
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int u = 0; u < kVecRows; ++u) asm volatile("" ::"v"(val[a][u]));
+}
+
 // p = z + beta p
 // (several grids: a converged grid's block returns before loading; the
 // flag of each system is otherwise checked only before the stores)
@@ -1502,22 +1533,17 @@ __global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ 
     const int v = threadIdx.x % R;
     const int sys = e.grid * R + v;
     if (tab && sc.done[sys]) return;
-    const int dn = sc.done[sys];
+    if (e.count <= 0) return;
+    int64_t o[kVecRows];
+    const double *src[2] = {z, p};
+    double val[2][kVecRows];
+    vec_rows<R, 2>(e, v, o, src, val);
     const double beta = sc.beta[sys];
-    double pn[kVecRows];
+    if (sc.done[sys]) return;
 #pragma unroll
     for (int u = 0; u < kVecRows; ++u) {
         const int rl = threadIdx.x / R + u * (kBlock / R);
-        if (rl < e.count) {
-            const int64_t o = (e.row0 + rl) * R + v;
-            pn[u] = z[o] + beta * p[o];
-        }
-    }
-    if (dn) return;
-#pragma unroll
-    for (int u = 0; u < kVecRows; ++u) {
-        const int rl = threadIdx.x / R + u * (kBlock / R);
-        if (rl < e.count) p[(e.row0 + rl) * R + v] = pn[u];
+        if (rl < e.count) p[o[u]] = val[0][u] + beta * val[1][u];
     }
 }
 
@@ -1596,20 +1622,24 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, co
     if (tab && grid_done<R>(sc.done, e.grid)) return;
     const int v = threadIdx.x % R;
     const int sys = e.grid * R + v;
-    const int dn = sc.done[sys];
-    const double alpha = sc.alpha[sys];
     double acc = 0.0;
+    if (e.count > 0) {
+        int64_t o[kVecRows];
+        const double *src[4] = {x, p, r, q};
+        double val[4][kVecRows];
+        vec_rows<R, 4>(e, v, o, src, val);
+        const double alpha = sc.alpha[sys];
+        if (!sc.done[sys]) {
 #pragma unroll
-    for (int u = 0; u < kVecRows; ++u) {
-        const int rl = threadIdx.x / R + u * (kBlock / R);
-        if (rl < e.count) {
-            const int64_t o = (e.row0 + rl) * R + v;
-            const double xi = x[o] + alpha * p[o];
-            const double ri = r[o] - alpha * q[o];
-            if (!dn) {
-                x[o] = xi;
-                r[o] = ri;
-                acc += ri * ri;
+            for (int u = 0; u < kVecRows; ++u) {
+                const int rl = threadIdx.x / R + u * (kBlock / R);
+                if (rl < e.count) {
+                    const double xi = val[0][u] + alpha * val[1][u];
+                    const double ri = val[2][u] - alpha * val[3][u];
+                    x[o[u]] = xi;
+                    r[o[u]] = ri;
+                    acc += ri * ri;
+                }
             }
         }
     }
