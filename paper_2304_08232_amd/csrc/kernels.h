@@ -64,7 +64,8 @@ hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_finalize_rz(const mgpcg_problem *P, hipStream_t s);  // rho from the fused partials
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s);
-hipError_t launch_update_xr(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s);
+hipError_t launch_update_r(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s);
+hipError_t launch_flush_x(const mgpcg_problem *P, hipStream_t s);  // x += pending alpha p, after the last iteration
 
 hipError_t launch_theta_grad(const double *lam, const double *x, const double *theta, double *grad,
                              int64_t n, hipStream_t s);

@@ -1523,27 +1523,53 @@ __device__ __forceinline__ void vec_rows(const Seg &e, int v, int64_t (&o)[kVecR
         for (int u = 0; u < kVecRows; ++u) asm volatile("" ::"v"(val[a][u]));
 }
 
-// p = z + beta p
-// (several grids: a converged grid's block returns before loading; the
-// flag of each system is otherwise checked only before the stores)
+// x += apend p (the previous iteration's x update, deferred to here, where
+// p is read anyway), then p = z + beta p.  apend is that iteration's alpha,
+// or 0 when nothing is pending (first iteration, or a system that had
+// converged before it); a system that converged in it still gets its x
+// update, but keeps its p.
+// (several grids: a grid whose systems had all converged before the previous
+// iteration has nothing pending and returns before loading)
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ z, double *__restrict__ p,
-                                                     const Seg *__restrict__ tab, int64_t nrows, Scalars sc) {
+                                                     double *__restrict__ x, const Seg *__restrict__ tab,
+                                                     int64_t nrows, Scalars sc) {
     const Seg e = vec_seg(tab, xcd_remap(blockIdx.x, gridDim.x), nrows, kVecRows * kBlock / R);
     const int v = threadIdx.x % R;
     const int sys = e.grid * R + v;
-    if (tab && sc.done[sys]) return;
+    if (tab && sc.done[sys] && sc.apend[sys] == 0.0) return;
     if (e.count <= 0) return;
     int64_t o[kVecRows];
-    const double *src[2] = {z, p};
-    double val[2][kVecRows];
-    vec_rows<R, 2>(e, v, o, src, val);
-    const double beta = sc.beta[sys];
-    if (sc.done[sys]) return;
+    const double *src[3] = {z, p, x};
+    double val[3][kVecRows];
+    vec_rows<R, 3>(e, v, o, src, val);
+    const double beta = sc.beta[sys], ap = sc.apend[sys];
+    const int dn = sc.done[sys];
 #pragma unroll
     for (int u = 0; u < kVecRows; ++u) {
         const int rl = threadIdx.x / R + u * (kBlock / R);
-        if (rl < e.count) p[o[u]] = val[0][u] + beta * val[1][u];
+        if (rl < e.count) {
+            if (ap != 0.0) x[o[u]] = val[2][u] + ap * val[1][u];
+            if (!dn) p[o[u]] = val[0][u] + beta * val[1][u];
+        }
+    }
+}
+
+// After the last iteration: the pending x update, x += apend p.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_flush_x(double *__restrict__ x, const double *__restrict__ p,
+                                                    const Seg *__restrict__ tab, int64_t nrows, Scalars sc) {
+    const Seg e = vec_seg(tab, xcd_remap(blockIdx.x, gridDim.x), nrows, kVecRows * kBlock / R);
+    const int v = threadIdx.x % R;
+    const double ap = sc.apend[e.grid * R + v];
+    if (ap == 0.0) return;
+#pragma unroll
+    for (int u = 0; u < kVecRows; ++u) {
+        const int rl = threadIdx.x / R + u * (kBlock / R);
+        if (rl < e.count) {
+            const int64_t o = (e.row0 + rl) * R + v;
+            x[o] = x[o] + ap * p[o];
+        }
     }
 }
 
@@ -1610,13 +1636,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
     store_partial<R>(acc, blk, partials);
 }
 
-// x += alpha p; r -= alpha q; partial ||r||^2
-// (converged systems: as in k_update_p; their x and r are not written)
+// r -= alpha q; partial ||r||^2 (the x update x += alpha p is deferred to
+// the next k_update_p, or to k_flush_x after the last iteration)
+// (converged systems: as in k_update_p; their r is not written)
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, const double *__restrict__ p,
-                                                      double *__restrict__ r, const double *__restrict__ q,
-                                                      const Seg *__restrict__ tab, int64_t nrows,
-                                                      double *__restrict__ partials, Scalars sc) {
+__global__ __launch_bounds__(kBlock) void k_update_r(double *__restrict__ r, const double *__restrict__ q,
+                                                     const Seg *__restrict__ tab, int64_t nrows,
+                                                     double *__restrict__ partials, Scalars sc) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const Seg e = vec_seg(tab, blk, nrows, kVecRows * kBlock / R);
     if (tab && grid_done<R>(sc.done, e.grid)) return;
@@ -1625,18 +1651,16 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(double *__restrict__ x, co
     double acc = 0.0;
     if (e.count > 0) {
         int64_t o[kVecRows];
-        const double *src[4] = {x, p, r, q};
-        double val[4][kVecRows];
-        vec_rows<R, 4>(e, v, o, src, val);
+        const double *src[2] = {r, q};
+        double val[2][kVecRows];
+        vec_rows<R, 2>(e, v, o, src, val);
         const double alpha = sc.alpha[sys];
         if (!sc.done[sys]) {
 #pragma unroll
             for (int u = 0; u < kVecRows; ++u) {
                 const int rl = threadIdx.x / R + u * (kBlock / R);
                 if (rl < e.count) {
-                    const double xi = val[0][u] + alpha * val[1][u];
-                    const double ri = val[2][u] - alpha * val[3][u];
-                    x[o[u]] = xi;
+                    const double ri = val[0][u] - alpha * val[1][u];
                     r[o[u]] = ri;
                     acc += ri * ri;
                 }
@@ -1689,6 +1713,10 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
     const double rho_old = KIND == kRz ? sc.rho_old[sys] : 0.0;
     const double rho = KIND == kPq ? sc.rho[sys] : 0.0;
     const double nr0 = KIND == kRr ? sc.nr0[sys] : 0.0;
+    const double alpha = KIND == kRr ? sc.alpha[sys] : 0.0;
+    // the deferred x update of the previous iteration was applied by the
+    // k_update_p that ran before this reduction: nothing is pending now
+    if (KIND == kPq && threadIdx.x < R) sc.apend[sys] = 0.0;
     double s = 0.0;
     while (b < b1) {
 #pragma unroll
@@ -1731,6 +1759,9 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
             sc.alpha[sys] = rho / tot;
         }
     } else {
+        // this iteration's x update, applied by the next k_update_p (or by
+        // k_flush_x), also when the system converges now
+        sc.apend[sys] = alpha;
         const int k = it0 + 1;
         sc.iter[sys] = k;
         const double rel = sqrt(tot) / nr0;
@@ -1813,9 +1844,18 @@ hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s) {
 hipError_t launch_finalize_rz(const mgpcg_problem *P, hipStream_t s) { return finalize<kRz>(P, 2, 0.0, 0, s); }
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s) {
     const bool one = P->G == 1;
-    MG_DISPATCH_R(P->R, (k_update_p<RR><<<P->n_red[1], kBlock, 0, s>>>(P->z, P->p, one ? nullptr : P->red_tab[1],
-                                                                       P->lev[0].n, P->sc)));
+    MG_DISPATCH_R(P->R, (k_update_p<RR><<<P->n_red[1], kBlock, 0, s>>>(P->z, P->p, P->x,
+                                                                       one ? nullptr : P->red_tab[1], P->lev[0].n,
+                                                                       P->sc)));
     return hipGetLastError();
+}
+hipError_t launch_flush_x(const mgpcg_problem *P, hipStream_t s) {
+    const bool one = P->G == 1;
+    MG_DISPATCH_R(P->R, (k_flush_x<RR><<<P->n_red[1], kBlock, 0, s>>>(P->x, P->p, one ? nullptr : P->red_tab[1],
+                                                                      P->lev[0].n, P->sc)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_fill_d(P->sc.apend, P->S, 0.0, s);
 }
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
@@ -1829,11 +1869,10 @@ hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     if (e != hipSuccess) return e;
     return finalize<kPq>(P, 0, 0.0, 0, s);
 }
-hipError_t launch_update_xr(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s) {
+hipError_t launch_update_r(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s) {
     const bool one = P->G == 1;
-    MG_DISPATCH_R(P->R, (k_update_xr<RR><<<P->n_red[1], kBlock, 0, s>>>(P->x, P->p, P->r, P->q,
-                                                                        one ? nullptr : P->red_tab[1], P->lev[0].n,
-                                                                        P->sc.partials, P->sc)));
+    MG_DISPATCH_R(P->R, (k_update_r<RR><<<P->n_red[1], kBlock, 0, s>>>(P->r, P->q, one ? nullptr : P->red_tab[1],
+                                                                       P->lev[0].n, P->sc.partials, P->sc)));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kRr>(P, 1, tol, hist_cap, s);

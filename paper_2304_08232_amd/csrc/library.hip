@@ -631,6 +631,7 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         ST_TRY(dalloc(&sc.beta, S));
         ST_TRY(dalloc(&sc.nr0, S));
         ST_TRY(dalloc(&sc.pq, S));
+        ST_TRY(dalloc(&sc.apend, S));
         ST_TRY(dalloc(&sc.iter, S));
         ST_TRY(dalloc(&sc.done, S));
         ST_TRY(dalloc(&sc.status, S));
@@ -773,7 +774,7 @@ void free_problem(mgpcg_problem *P) {
     dfree(P->red_gb[2]);
     dfree(P->x); dfree(P->r); dfree(P->z); dfree(P->p); dfree(P->q); dfree(P->b);
     Scalars &sc = P->sc;
-    dfree(sc.rho); dfree(sc.rho_old); dfree(sc.alpha); dfree(sc.beta); dfree(sc.nr0); dfree(sc.pq);
+    dfree(sc.rho); dfree(sc.rho_old); dfree(sc.alpha); dfree(sc.beta); dfree(sc.nr0); dfree(sc.pq); dfree(sc.apend);
     dfree(sc.iter); dfree(sc.done); dfree(sc.status); dfree(sc.ndone);
     dfree(sc.partials);
     dfree(P->fold);
@@ -924,7 +925,7 @@ hipError_t cg_iteration(mgpcg_problem *P, double tol, hipStream_t s) {
     if ((e = P->fuse_rz ? launch_finalize_rz(P, s) : launch_dot_rz(P, s)) != hipSuccess) return e;
     if ((e = launch_update_p(P, s)) != hipSuccess) return e;
     if ((e = launch_spmv_pq(P, s)) != hipSuccess) return e;
-    return launch_update_xr(P, tol, P->hist_cap, s);
+    return launch_update_r(P, tol, P->hist_cap, s);
 }
 
 // ------------------------------------------------------- argument helpers
@@ -1576,6 +1577,7 @@ mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int m
     HIP_TRY(launch_fill_i(sc.iter, S, 0, s));
     HIP_TRY(launch_fill_i(sc.ndone, 1, 0, s));
     HIP_TRY(launch_fill_d(sc.rho_old, S, 0.0, s));
+    HIP_TRY(launch_fill_d(sc.apend, S, 0.0, s));
     HIP_TRY(launch_fill_d(p->hist, (int64_t)S * p->hist_cap, 0.0, s));
     HIP_TRY(launch_fill_d(p->p, n, 0.0, s));
     HIP_TRY(launch_init_residual(p, s));
@@ -1630,6 +1632,8 @@ mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int m
             ++tail;
         }
     }
+    // the last iteration's x update (each iteration's is applied by the next)
+    HIP_TRY(launch_flush_x(p, s));
     ST_TRY(out_vec(p, 0, p->x, x, layout, s));
     if (!history_host && !iters_host && rel_tol == 0.0) return MGPCG_OK;
     return fetch_result(p, max_iters, history_host, iters_host, s);

@@ -184,6 +184,7 @@ struct CoarseArgs {
 
 struct Scalars {  // per-system CG state, device arrays of S entries
     double *rho, *rho_old, *alpha, *beta, *nr0, *pq;
+    double *apend;       // alpha of the x update still pending (0: none)
     int *iter, *done, *status;
     int *ndone;          // one counter: systems finished
     double *partials;    // reduction blocks * R

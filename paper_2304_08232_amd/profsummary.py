@@ -169,7 +169,7 @@ def classify(short, grid, maps, levels):
         return "?", "zero fill"
     if base == "k_spmv_pq":
         return "CG", "CG SpMV + <p,q>"
-    if base in ("k_update_p", "k_update_xr", "k_dot_rz"):
+    if base in ("k_update_p", "k_update_r", "k_flush_x", "k_dot_rz"):
         return "CG", "CG vector updates and dots"
     if base in ("k_finalize", "k_fold"):
         return "CG", "CG reductions (finalize)"

@@ -176,6 +176,43 @@ def test_pcg_tolerance_stop_and_status(mg):
     assert st == mg.ERR_BREAKDOWN and its[0] == 0
 
 
+@pytest.mark.parametrize("dims,nrhs", [((24, 16, 32), 1), ((64, 64, 64), 1), ((16, 16, 16), 4)])
+def test_iterations_after_convergence_change_nothing(mg, dims, nrhs):
+    # A tolerance-driven solve reads the count of finished systems only once
+    # a later iteration is queued, so iterations run after the last system
+    # converged; with one grid the colour passes store regardless of the
+    # flag, and the CG updates and finalizes must leave x, r, p and the
+    # scalars of a converged system alone.  The solve must therefore give,
+    # bit for bit, the x and history of a fixed-count solve of exactly the
+    # iterations it reports.
+    n = dims[0] * dims[1] * dims[2]
+    p = mg.Problem(dims, nrhs=nrhs)
+    b = dev(inputs.uniform(15, n * nrhs))
+    for graph in (1, 0):
+        p.set_graph_mode(graph)
+        x, h, its, st = p.solve(b, max_iters=300, tol=1e-9)
+        assert st == mg.OK and len(set(int(k) for k in its)) >= 1
+        k = int(max(its))
+        xf, hf, itsf, stf = p.solve(b, max_iters=k, tol=0.0)
+        if nrhs == 1:
+            assert int(itsf[0]) == k
+            assert torch.equal(x, xf), f"graph {graph}: x moved after convergence"
+            assert np.array_equal(h[0, :k], hf[0, :k])
+        else:
+            # right-hand sides that converged earlier stop early in the
+            # tolerance solve and run on in the fixed-count one: compare the
+            # last-converging ones, and the others' histories up to their stop
+            last = [v for v in range(nrhs) if int(its[v]) == k]
+            # natural layout holds the right-hand sides one after another
+            X, XF = host(x).reshape(nrhs, -1), host(xf).reshape(nrhs, -1)
+            for v in last:
+                assert np.array_equal(X[v], XF[v]), f"graph {graph}, rhs {v}"
+            for v in range(nrhs):
+                kv = int(its[v])
+                assert np.array_equal(h[v, :kv], hf[v, :kv]), f"graph {graph}, rhs {v}"
+                assert np.all(h[v, kv:] == 0)
+
+
 def test_pcg_nonzero_x0(mg):
     o = Oracle(16, 16, 16)
     p = mg.Problem((16, 16, 16))
