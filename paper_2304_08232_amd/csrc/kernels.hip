@@ -29,6 +29,43 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * per + (x < rem ? x : rem) + q;
 }
 
+// Workgroup order of a one-grid colour pass with several right-hand sides.
+// A point then carries 8R bytes, and the rows an XCD has in flight (about a
+// half-plane of the colour in row order) gather from three fine planes, more
+// than its L2 holds, so neighbour values are fetched again.  Here each XCD's
+// z-slab of the colour is visited in y-blocks of `yb` half-lines, all of the
+// slab's half-planes per block, so the rows in flight form a compact box.
+// Rows of one colour are independent: the order changes no result.
+struct PassGeo {
+    int32_t hxq = 0;    // workgroups per half-line (0: row order)
+    int32_t hy = 0;     // half-lines per half-plane
+    int32_t zs = 0;     // half-planes per slab (one slab per XCD)
+    int32_t yb = 0;     // half-lines per y-block (divides hy)
+    int32_t split = 0;  // two colours of equal extents (the fused zero-start
+                        // pass): the first workgroup of the second (0: one)
+};
+
+// row block (in units of the pass's rows per workgroup, from the first row of
+// the range) of logical workgroup p
+__device__ __forceinline__ int64_t geo_block(int p, const PassGeo &g) {
+    if (g.hxq == 0) return p;
+    int base = 0;
+    if (g.split && p >= g.split) {
+        base = g.split;
+        p -= g.split;
+    }
+    const int line = g.hxq, blk = g.yb * line, ybk = g.zs * blk, slab = g.hy * g.zs * line;
+    const int sl = p / slab;
+    int q = p - sl * slab;
+    const int y0 = q / ybk;
+    q -= y0 * ybk;
+    const int jz = q / blk;
+    q -= jz * blk;
+    const int jy = q / line;
+    const int jq = q - jy * line;
+    return base + ((int64_t)(sl * g.zs + jz) * g.hy + (int64_t)y0 * g.yb + jy) * line + jq;
+}
+
 __device__ __forceinline__ double softplus_d(double t) {
     return fmax(t, 0.0) + log1p(exp(-fabs(t)));
 }
@@ -576,6 +613,78 @@ __device__ __forceinline__ double pass_row(int64_t n, const T *__restrict__ val,
     return DOT ? (double)rv * (double)znew : 0.0;
 }
 
+// N consecutive values (N = 1 or 2) as one access
+template <typename T, int N>
+__device__ __forceinline__ void ld_lanes(const T *p, T (&v)[N]) {
+    if constexpr (N == 2) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        const V2 t = *(const V2 *)p;
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        v[0] = *p;
+    }
+}
+template <typename T, int N>
+__device__ __forceinline__ void st_lanes(T *p, const T (&v)[N]) {
+    if constexpr (N == 2) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        *(V2 *)p = V2{v[0], v[1]};
+    } else {
+        *p = v[0];
+    }
+}
+
+// The update of one row for two right-hand sides (2w and 2w+1) in one lane
+// (R >= kPairR, values staged in LDS): r, z, the gathers and the coarse
+// values move as 16-byte pairs, which halves the per-lane address work of a
+// pass whose texture unit is otherwise its bottleneck.  Each right-hand
+// side's arithmetic is exactly pass_row's.
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, class SB, bool TWICE>
+__device__ __forceinline__ void pass_row2(int64_t n, const int32_t *__restrict__ col,
+                                          const int8_t *__restrict__ dcol, const SB &sb, const T *__restrict__ r,
+                                          T *z, int64_t i, int w, int64_t inj_base, T *__restrict__ coarse,
+                                          const int32_t *__restrict__ inj_coarse, const T *vs, int vstride) {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const int64_t o = i * R + 2 * w;
+    const V2 rv = *(const V2 *)(r + o);
+    int64_t co = 0;
+    if (MODE != 0) co = (int64_t)inj_coarse[i - inj_base] * R + 2 * w;
+    T a[kW];
+    int32_t c[kW];
+    load_slots<T, R, SKIP, NT, CF, SB, true>(nullptr, col, dcol, sb, n, i, a, c, vs, vstride);
+    V2 xv[kW];
+#pragma unroll
+    for (int s = 0; s < kW; ++s) {
+        const bool sk = (SKIP >> s) & 1u;
+        xv[s] = !sk ? *(const V2 *)(z + (int64_t)c[s] * R + 2 * w) : V2{T(0), T(0)};
+    }
+    V2 zc = {T(0), T(0)};
+    if (MODE == 2) zc = *(const V2 *)(coarse + co);
+    V2 zi = SKIP ? V2{T(0), T(0)} : (MODE == 2 ? xv[kCentre] + zc : xv[kCentre]);
+    if (MODE == 2) xv[kCentre] = zi;
+    const auto x0 = [&](int s) { return xv[s].x; };
+    const auto x1 = [&](int s) { return xv[s].y; };
+    V2 zn;
+    zn.x = gs_update<T, SKIP>(a, x0, rv.x, zi.x);
+    zn.y = gs_update<T, SKIP>(a, x1, rv.y, zi.y);
+    if constexpr (TWICE) {
+        V2 z2;
+        z2.x = gs_again(a, x0, rv.x, zn.x);
+        z2.y = gs_again(a, x1, rv.y, zn.y);
+        *(V2 *)(z + o) = z2;
+        return;
+    }
+    *(V2 *)(z + o) = zn;
+    if (MODE == 1) {
+        xv[kCentre] = zn;
+        V2 rc;
+        rc.x = rv.x - row_dot<T, 0u>(a, x0);
+        rc.y = rv.y - row_dot<T, 0u>(a, x1);
+        *(V2 *)(coarse + co) = rc;
+    }
+}
+
 // DOT (one grid, no table): each workgroup also writes the sum of r_i z_i
 // over its rows to rzp[b * R + rhs].
 template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, bool TWICE = false, bool DOT = false>
@@ -586,7 +695,8 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
                                                  const Seg *__restrict__ tab, int64_t row_base,
                                                  int64_t row_end, const int *__restrict__ done,
                                                  T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
-                                                 double *__restrict__ rzp, const int32_t *__restrict__ gbase) {
+                                                 double *__restrict__ rzp, const int32_t *__restrict__ gbase,
+                                                 const PassGeo geo) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
@@ -603,9 +713,30 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
             for (int t = 0; t < kW; ++t) sb.v[t] = gb[t];
         }
     } else {
-        row0 = row_base + (int64_t)b * (pass_block(NT) / R);
+        row0 = row_base + geo_block(b, geo) * pass_rows(NT, R);
         count = row_end - row0;
         grid = 0;
+    }
+    if constexpr (R >= kPairR) {
+        // R/2 lanes per row, two right-hand sides each; the workgroup's
+        // values go through LDS once
+        constexpr int LN = pass_lanes(R), RW = pass_rows(NT, R);
+        __shared__ T sv[kW * RW];
+        const int rl = threadIdx.x / LN, w = threadIdx.x % LN;
+        if (tab && done) {  // a grid whose systems are all converged: uniform, before the barrier
+            bool all = true;
+#pragma unroll
+            for (int u = 0; u < R; ++u) all = all && done[grid * R + u];
+            if (all) return;
+        }
+        stage_values<T, SKIP, NT, RW, pass_block(NT)>(val, row0, count, sv);
+        if (rl >= count) return;
+        // several grids: a lane whose two systems have both converged stores
+        // nothing (z is internal: a converged system's z is never used again)
+        if (tab && done && done[grid * R + 2 * w] && done[grid * R + 2 * w + 1]) return;
+        pass_row2<T, R, SKIP, NT, MODE, CF, Base27, TWICE>(n, col, dcol, sb, r, z, row0 + rl, w, row_base, coarse,
+                                                       inj_coarse, sv + rl, RW);
+        return;
     }
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
     if constexpr (DOT) {
@@ -634,7 +765,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
     } else {
         if (rl >= count) return;
         // several grids: a converged grid is skipped before anything is
-        // loaded; one grid: its flag travels with the loads
+        // loaded (one grid: the host passes no flag)
         if (tab && done && done[grid * R + v]) return;
         pass_row<T, R, SKIP, NT, MODE, CF, Base27, TWICE>(n, val, col, dcol, sb, r, z, row0 + rl, v, row_base,
                                                          coarse, inj_coarse, tab || !done ? nullptr : done + v);
@@ -653,7 +784,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
                                                       const T *__restrict__ r, T *__restrict__ z,
                                                       const Seg *__restrict__ tab, int64_t coff0, int64_t coff1,
                                                       int64_t coff2, const int *__restrict__ done,
-                                                      const int32_t *__restrict__ gbase) {
+                                                      const int32_t *__restrict__ gbase, const PassGeo geo) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
@@ -669,58 +800,78 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
             for (int t = 0; t < kW; ++t) sb1.v[t] = gb[t];
         }
     } else {
-        row0 = coff0 + (int64_t)b * (pass_block(NT) / R);
+        row0 = coff0 + geo_block(b, geo) * pass_rows(NT, R);
         count = coff2 - row0;
         grid = 0;
     }
-    const int rl = threadIdx.x / R, v = threadIdx.x % R;
+    // R >= kPairR: each lane updates two right-hand sides (as in k_pass)
+    constexpr int LN = pass_lanes(R), NV = R / LN;
+    const int rl = threadIdx.x / LN, w = threadIdx.x % LN;
     if (rl >= count) return;
-    if (tab && done && done[grid * R + v]) return;  // as in k_pass
-    const int dv = (!tab && done) ? done[v] : 0;
+    if (tab && done) {  // as in k_pass
+        bool all = true;
+#pragma unroll
+        for (int u = 0; u < NV; ++u) all = all && done[grid * R + NV * w + u];
+        if (all) return;
+    }
+    // one grid: the host passes no flag (z is internal)
+    const int dv = (!tab && done && NV == 1) ? done[w] : 0;
     const int64_t i = row0 + rl;
-    const int64_t o = i * R + v;
-    const T rv = r[o];
+    const int64_t o = i * R + NV * w;
+    T rv[NV], zn[NV];
+    ld_lanes(r + o, rv);
     if (i < coff1) {
         const T d = ld<NT>(val + ell_index(kCentre, i));
         const T acc = T(0), zi = T(0);
-        if (!dv) z[o] = (rv - acc + zi * d) / d;
+#pragma unroll
+        for (int u = 0; u < NV; ++u) zn[u] = (rv[u] - acc + zi * d) / d;
+        if (!dv) st_lanes(z + o, zn);
         return;
     }
     constexpr uint32_t SKIP = zs_mask(1, ORD);
     T a[kW];
     int32_t c[kW];
     load_slots<T, R, SKIP, NT, CF>(val, col, dcol, sb1, n, i, a, c);
-    T rj[kW], dj[kW];
+    T rj[kW][NV], dj[kW];
 #pragma unroll
     for (int s = 0; s < kW; ++s) {
         const bool sk = (SKIP >> s) & 1u;
         const bool use = !sk && a[s] != T(0);
-        rj[s] = use ? r[(int64_t)c[s] * R + v] : T(0);
+        if (use) {
+            ld_lanes(r + (int64_t)c[s] * R + NV * w, rj[s]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < NV; ++u) rj[s][u] = T(0);
+        }
         dj[s] = use ? val[ell_index(kCentre, c[s])] : T(1);
     }
     const T d = a[kCentre];
-    T acc = 0;
 #pragma unroll
-    for (int s = 0; s < kW; ++s) {
-        const bool sk = (SKIP >> s) & 1u;
-        if (!sk && a[s] != T(0)) {
-            const T acc0 = T(0), z0 = T(0);
-            const T zj = (rj[s] - acc0 + z0 * dj[s]) / dj[s];  // the colour-0 value of the first pass
-            acc = acc + a[s] * zj;
+    for (int u = 0; u < NV; ++u) {
+        T acc = 0;
+#pragma unroll
+        for (int s = 0; s < kW; ++s) {
+            const bool sk = (SKIP >> s) & 1u;
+            if (!sk && a[s] != T(0)) {
+                const T acc0 = T(0), z0 = T(0);
+                const T zj = (rj[s][u] - acc0 + z0 * dj[s]) / dj[s];  // the colour-0 value of the first pass
+                acc = acc + a[s] * zj;
+            }
         }
+        const T zi = T(0);
+        zn[u] = (rv[u] - acc + zi * d) / d;
     }
-    const T zi = T(0);
-    if (!dv) z[o] = (rv - acc + zi * d) / d;
+    if (!dv) st_lanes(z + o, zn);
 }
 
 template <typename T, int R, bool NT, int CF>
 static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T *val, const int32_t *col,
                     const int8_t *dcol, const Base27 &sb, const T *r, T *z, const Seg *tab, int64_t rb,
-                    int64_t re, const int *done, const int32_t *gb) {
+                    int64_t re, const int *done, const int32_t *gb, const PassGeo &geo) {
 #define MG_ZS_CASE(K, O)                                                                              \
     case K + 8 * O:                                                                                   \
         k_pass<T, R, zs_mask(K, O), NT, 0, CF><<<cnt, pass_block(NT), 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
-                                                                      done, nullptr, nullptr, nullptr, gb); \
+                                                                      done, nullptr, nullptr, nullptr, gb, geo); \
         break;
     switch (k + 8 * order) {
         MG_ZS_CASE(0, 0) MG_ZS_CASE(1, 0) MG_ZS_CASE(2, 0) MG_ZS_CASE(3, 0)
@@ -735,6 +886,22 @@ static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T
 uint32_t standard_zs_mask(int k, int order) { return zs_mask(k, order); }
 static_assert(zs_mask(7, 0) == (1u << kCentre) && zs_mask(7, 1) == (1u << kCentre),
               "the last colour of a zero-start sweep reads every neighbour");
+
+// Workgroup order of a one-grid pass over colour k whose rows split into
+// nslab equal z-slabs (see PassGeo); row order when it does not apply.
+static PassGeo pass_geo(const mgpcg_problem *P, const Level &L, int k, int nslab) {
+    PassGeo g;
+    if (P->G != 1 || P->R < 2 || P->pass_yblock <= 0) return g;
+    const int rows = pass_rows(L.stream_nt, P->R);
+    const int32_t *h = L.grids[0].half[k];
+    const int yb = std::min<int>(P->pass_yblock, h[1]);
+    if (rows <= 0 || yb <= 0 || h[0] % rows || h[2] % nslab || h[1] % yb) return g;
+    g.hxq = h[0] / rows;
+    g.hy = h[1];
+    g.zs = h[2] / nslab;
+    g.yb = yb;
+    return g;
+}
 
 template <typename T>
 hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
@@ -760,13 +927,14 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         cnt = L.pass_first[k + 1] - first;
         tab = L.pass_tab + first;
     } else {
-        const int rows = pass_block(L.stream_nt) / R;
+        const int rows = pass_rows(L.stream_nt, R);
         cnt = (int)((re - rb + rows - 1) / rows);
     }
     if (cnt == 0) return hipSuccess;
     const int32_t *ic = L.inj_coarse;
     Base27 sb;
     for (int t = 0; t < kW; ++t) sb.v[t] = L.cf ? L.dbase_host[k * kW + t] : 0;
+    const PassGeo geo = pass_geo(P, L, k, kXcd);
     if (mode == kPassZeroStart01) {
         if (k != 0 || !L.zs_std || L.ncol != 8 || (R != 1 && R != 16)) return hipErrorInvalidValue;
         int cnt01;
@@ -775,18 +943,27 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
             tab01 = L.pass_tab + L.pass_first[0];
             cnt01 = L.pass_first[2] - L.pass_first[0];
         } else {
-            const int rows = pass_block(L.stream_nt) / R;
+            const int rows = pass_rows(L.stream_nt, R);
             cnt01 = (int)((L.coff[2] - L.coff[0] + rows - 1) / rows);
         }
         Base27 sb1;
         for (int t = 0; t < kW; ++t) sb1.v[t] = L.cf ? L.dbase_host[1 * kW + t] : 0;
+        // colours 0 and 1 each over half of the XCDs
+        PassGeo geo01 = pass_geo(P, L, 0, kXcd / 2);
+        if (geo01.hxq) {
+            const int32_t *h0 = L.grids[0].half[0], *h1 = L.grids[0].half[1];
+            if (h0[0] == h1[0] && h0[1] == h1[1] && h0[2] == h1[2])
+                geo01.split = geo01.hxq * h0[1] * h0[2];
+            else
+                geo01 = PassGeo{};
+        }
 #define MG_ZS01(RR, NT, CF)                                                                             \
     if (P->colour_order)                                                                               \
         k_pass_zs01<T, RR, NT, CF, 1><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
-                                                            L.coff[0], L.coff[1], L.coff[2], done, gb);  \
+                                                            L.coff[0], L.coff[1], L.coff[2], done, gb, geo01); \
     else                                                                                               \
         k_pass_zs01<T, RR, NT, CF, 0><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
-                                                            L.coff[0], L.coff[1], L.coff[2], done, gb);
+                                                            L.coff[0], L.coff[1], L.coff[2], done, gb, geo01);
 #define MG_ZS01_R(NT, CF)                                                                               \
     if (R == 1) { MG_ZS01(1, NT, CF) } else { MG_ZS01(16, NT, CF) }
         if (L.stream_nt) {
@@ -806,10 +983,10 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (rzp && SKIPM == 0u) {                                                                          \
         if constexpr (sizeof(T) == 8)                                                                  \
             MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true, true><<<cnt, pass_block(NT), 0, s>>>(  \
-                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp, gb))); \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp, gb, geo))); \
     } else {                                                                                           \
         MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true><<<cnt, pass_block(NT), 0, s>>>(            \
-                             L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr, gb))); \
+                             L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr, gb, geo))); \
     }
 #define MG_TWICE_MODE(SKIPM)                                                                            \
     if (L.stream_nt) {                                                                                 \
@@ -830,8 +1007,8 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         if (!L.zs_std || (R != 1 && R != 16)) return hipErrorInvalidValue;
         const int ord = P->colour_order;
 #define MG_ZS_LAUNCH(NT, CF)                                                                           \
-    if (R == 1) pass_zs<T, 1, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb); \
-    else pass_zs<T, 16, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb);
+    if (R == 1) pass_zs<T, 1, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb, geo); \
+    else pass_zs<T, 16, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb, geo);
         if (L.stream_nt) {
             if (L.cf == 2) { MG_ZS_LAUNCH(true, 2) } else if (L.cf == 1) { MG_ZS_LAUNCH(true, 1) } else { MG_ZS_LAUNCH(true, 0) }
         } else {
@@ -844,11 +1021,11 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (M == 0 && rzp) {                                                                               \
         if constexpr (sizeof(T) == 8)                                                                  \
             MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, 0, CF, false, true><<<cnt, pass_block(NT), 0, s>>>(    \
-                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp, gb))); \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp, gb, geo))); \
     } else {                                                                                           \
         MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, CF><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, \
                                                                           r, z, tab, rb, re, done, coarse, ic, \
-                                                                          nullptr, gb)));         \
+                                                                          nullptr, gb, geo)));    \
     }
 #define MG_PASS_MODE(M)                                                                                \
     if (L.stream_nt) {                                                                                 \
@@ -1424,6 +1601,55 @@ __device__ __forceinline__ Seg vec_seg(const Seg *__restrict__ tab, int blk, int
     return e;
 }
 
+// Per-workgroup partials of the paired-lane kernels (R >= kPairR, R/2 lanes
+// per row): lane w holds the sums of right-hand sides 2w and 2w+1; partials
+// are written to partials[blk * R + rhs] like store_partial's.
+template <int R>
+__device__ __forceinline__ void store_partial2(double acc0, double acc1, int blk, double *partials) {
+    constexpr int LN = pass_lanes(R);
+    __shared__ double sh[(kBlock / 64) * R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= LN; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off, 64);
+        acc1 += __shfl_xor(acc1, off, 64);
+    }
+    __syncthreads();
+    if (lane < LN) {
+        sh[wv * R + 2 * lane] = acc0;
+        sh[wv * R + 2 * lane + 1] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double t = sh[threadIdx.x];
+#pragma unroll
+        for (int k = 1; k < kBlock / 64; ++k) t += sh[k * R + threadIdx.x];
+        partials[(int64_t)blk * R + threadIdx.x] = t;
+    }
+}
+
+// sum_j a_ij x_j of row i for right-hand sides 2w and 2w+1 (values staged in
+// LDS), each in row_sum's slot order
+template <int R, int CF, class SB>
+__device__ __forceinline__ void row_sum2(const int32_t *__restrict__ col, const int8_t *__restrict__ dcol,
+                                         const SB &sb, int64_t n, int64_t i, const double *x, int w,
+                                         const double *vs, int vstride, double (&s2)[2]) {
+    double a[kW];
+    int32_t c[kW];
+    load_slots<double, R, 0u, true, CF, SB, true>(nullptr, col, dcol, sb, n, i, a, c, vs, vstride);
+    double xv[kW][2];
+#pragma unroll
+    for (int t = 0; t < kW; ++t) ld_lanes(x + (int64_t)c[t] * R + 2 * w, xv[t]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        double acc = 0;
+#pragma unroll
+        for (int t = 0; t < kW; ++t)
+            if (a[t] != 0.0) acc = acc + a[t] * xv[t][u];
+        s2[u] = acc;
+    }
+}
+
 // SpMV-type kernels (one row per R threads, table 0): with one right-hand
 // side a workgroup takes one table entry of kBlock rows.  With R > 1 an entry
 // holds only kBlock/R rows, so a workgroup takes `spc` consecutive entries of
@@ -1442,6 +1668,32 @@ __global__ __launch_bounds__(kBlock) void k_init_residual(int64_t n, const doubl
                                                           double *__restrict__ r, const Seg *__restrict__ tab,
                                                           double *__restrict__ partials, int spc) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    if constexpr (R >= kPairR) {
+        // R/2 lanes per row, two right-hand sides each; values through LDS
+        constexpr int LN = pass_lanes(R), RW = kBlock / LN;
+        __shared__ double sv2[kW * RW];
+        const int w = threadIdx.x % LN, rl = threadIdx.x / LN;
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int it = 0; it < spc; ++it) {
+            const Seg e = tab[(int64_t)blk * spc + it];
+            stage_values<double, 0u, true, RW, kBlock>(val, e.row0, e.count, sv2);
+            if (rl < e.count) {
+                const int64_t i = e.row0 + rl;
+                const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+                double s2[2], bv[2], ri[2];
+                row_sum2<R, CF>(col, dcol, sb, n, i, x, w, sv2 + rl, RW, s2);
+                ld_lanes(b + i * R + 2 * w, bv);
+                ri[0] = bv[0] - s2[0];
+                ri[1] = bv[1] - s2[1];
+                st_lanes(r + i * R + 2 * w, ri);
+                acc0 += ri[0] * ri[0];
+                acc1 += ri[1] * ri[1];
+            }
+            __syncthreads();  // the next entry overwrites sv2
+        }
+        store_partial2<R>(acc0, acc1, blk, partials);
+        return;
+    }
     const int v = threadIdx.x % R, rl = threadIdx.x / R;
     double acc = 0.0;
     for (int it = 0; it < (R == 1 ? 1 : spc); ++it) {
@@ -1592,6 +1844,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
     const int64_t first = (int64_t)blk * (R == 1 ? 1 : spc);
     // the entries of a workgroup belong to one grid
     if (done && grid_done<R>(done, tab[first].grid)) return;  // done: NULL for one grid
+    if constexpr (R >= kPairR) {
+        // R/2 lanes per row, two right-hand sides each; values through LDS
+        constexpr int LN = pass_lanes(R), RW = kBlock / LN;
+        __shared__ double sv2[kW * RW];
+        const int w = threadIdx.x % LN, rl = threadIdx.x / LN;
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int it = 0; it < spc; ++it) {
+            const Seg e = tab[first + it];
+            stage_values<double, 0u, true, RW, kBlock>(val, e.row0, e.count, sv2);
+            if (rl < e.count) {
+                const int64_t i = e.row0 + rl;
+                const int32_t *sb = CF ? dbase + (e.grid * 8 + e.colour) * kW : nullptr;
+                double s2[2], pv[2];
+                row_sum2<R, CF>(col, dcol, sb, n, i, p, w, sv2 + rl, RW, s2);
+                st_lanes(q + i * R + 2 * w, s2);
+                ld_lanes(p + i * R + 2 * w, pv);
+                acc0 += pv[0] * s2[0];
+                acc1 += pv[1] * s2[1];
+            }
+            __syncthreads();  // the next entry overwrites sv2
+        }
+        store_partial2<R>(acc0, acc1, blk, partials);
+        return;
+    }
     const int v = threadIdx.x % R, rl = threadIdx.x / R;
     double acc = 0.0;
     for (int it = 0; it < (R == 1 ? 1 : spc); ++it) {

@@ -112,7 +112,7 @@ inline int64_t half_count(int ext, int bit) { return ext >= 2 ? (ext + 1 - bit) 
 // update of each colour; colour k's first at off[k] (off[8]: the count)
 void rz_layout(const mgpcg_problem *P, bool wide, int64_t *off) {
     const Level &L0 = P->lev[0];
-    const int rows = pass_block(wide) / P->R;
+    const int rows = pass_rows(wide, P->R);
     off[0] = 0;
     for (int k = 0; k < 8; ++k) off[k + 1] = off[k] + (L0.coff[k + 1] - L0.coff[k] + rows - 1) / rows;
 }
@@ -232,10 +232,14 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             Lv.ncol = std::max(Lv.ncol, C.ncol);
             for (int k = 0; k < 8; ++k) {
                 lg.seg_len[k] = 0;
+                lg.half[k][0] = lg.half[k][1] = lg.half[k][2] = 0;
                 if (k < C.ncol) {
                     int b[3];
                     C.parity(k, b);
-                    lg.seg_len[k] = half_count(lg.nx, b[0]) * half_count(lg.ny, b[1]) * half_count(lg.nz, b[2]);
+                    lg.half[k][0] = (int32_t)half_count(lg.nx, b[0]);
+                    lg.half[k][1] = (int32_t)half_count(lg.ny, b[1]);
+                    lg.half[k][2] = (int32_t)half_count(lg.nz, b[2]);
+                    lg.seg_len[k] = (int64_t)lg.half[k][0] * lg.half[k][1] * lg.half[k][2];
                 }
             }
             lg.inj_colour = C.colour(0, 0, 0);
@@ -332,12 +336,12 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         if (const char *env = getenv("MGPCG_NT_BYTES")) nt_bytes = atoll(env);  // tuning override
         Lv.stream_nt = opbytes > nt_bytes;
         // colour-pass tables, for both workgroup sizes: one workgroup per
-        // pass_block/R rows, grid-homogeneous
+        // pass_rows rows, grid-homogeneous
         for (int v = 0; v < 2; ++v) {
             std::vector<Seg> tab;
             std::vector<int> &first = Lv.pass_first_v[v];
             first.assign(Lv.ncol + 1, 0);
-            const int rows_per_block = pass_block(v == 1) / R;
+            const int rows_per_block = pass_rows(v == 1, R);
             for (int k = 0; k < Lv.ncol; ++k) {
                 first[k] = (int)tab.size();
                 for (int g = 0; g < G; ++g) {
@@ -519,7 +523,9 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         for (int t = 0; t < 2; ++t) {
             std::vector<Seg> tab;
             std::vector<int> gb(G + 1, 0);
-            const int rows = (t == 0 ? 1 : kVecRows) * kBlock / R;
+            // table 0: one row per pass_lanes(R) threads (two right-hand
+            // sides per lane from kPairR on, as in the colour passes)
+            const int rows = t == 0 ? kBlock / pass_lanes(R) : kVecRows * kBlock / R;
             const int per = t == 0 ? P->spc : 1;  // entries per workgroup
             if (t == 1 && G == 1) {
                 // one grid: the vector kernels take contiguous chunks of the
@@ -1300,6 +1306,8 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     P->dims0.assign(cfg->dims, cfg->dims + 3 * cfg->ngrids);
     // tuning and test override: 0 int32 columns, 1 at most int8 deltas, 2 (default) implied columns allowed
     if (const char *env = getenv("MGPCG_DELTA_COLS")) P->col_format = std::min(2, std::max(0, atoi(env)));
+    // tuning override: y-block of the multi-rhs colour passes (0: row order)
+    if (const char *env = getenv("MGPCG_PASS_YBLOCK")) P->pass_yblock = std::max(0, atoi(env));
     mgpcg_status st = build_hierarchy(P, cfg->theta, stream);
     if (st != MGPCG_OK) {
         std::string msg = g_err;

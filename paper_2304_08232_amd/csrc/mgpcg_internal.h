@@ -36,6 +36,12 @@ constexpr int kXcdCount = 8;     // XCDs of the part; workgroup b is dispatched 
 // one wavefront on cache-resident levels, whose passes are latency-bound, so
 // that their few rows are spread over as many CUs as possible.
 constexpr int pass_block(bool streamed) { return streamed ? 256 : 64; }
+// With R >= kPairR right-hand sides a colour-pass lane updates two of them
+// (16-byte accesses: half the address work per gathered byte), so a row has
+// R/2 lanes and a workgroup twice the rows.
+constexpr int kPairR = 4;
+constexpr int pass_lanes(int R) { return R >= kPairR ? R / 2 : R; }
+constexpr int pass_rows(bool streamed, int R) { return pass_block(streamed) / pass_lanes(R); }
 // threads of the single-workgroup coarsest-level kernel; it is used only when
 // every colour of that level has at most this many rows
 constexpr int kTailBlock = 512;
@@ -82,6 +88,7 @@ struct LevelGrid {  // one grid at one level
     int64_t nat_off;     // first row of this grid in the natural packed order
     int64_t seg_off[8];  // first internal row of (colour k, this grid)
     int64_t seg_len[8];  // rows of (colour k, this grid)
+    int32_t half[8][3];  // (x, y, z) extents of colour k's points: its rows run z, y, x (x fastest)
     int inj_colour;      // colour holding the injection points (2jx,2jy,2jz)
 };
 
@@ -111,7 +118,7 @@ struct Level {
 
     // colour-pass tables: entries of colour k are pass_tab[pass_first[k] .. pass_first[k+1]);
     // the active pair is variant [stream_nt] of pass_tab_v / pass_first_v
-    // (the segment length follows the workgroup size, pass_block(stream_nt))
+    // (the segment length follows the workgroup size, pass_rows(stream_nt, R))
     Seg *pass_tab = nullptr;
     std::vector<int> pass_first;
     Seg *pass_tab_v[2] = {nullptr, nullptr};
@@ -202,6 +209,10 @@ struct mgpcg_problem {
     int lex_run_rows = 256;  // sequential smoother: largest wavefront a single-workgroup run takes
     // most compact column format allowed (Level::cf), 2 by default
     int col_format = 2;
+    // one grid with several right-hand sides: the colour passes visit their
+    // rows in y-blocks of this many half-lines within each XCD's z-slab (0:
+    // in row order)
+    int pass_yblock = 0;
     std::vector<int> dims0;  // 3*G, level 0
     std::vector<mg::Level> lev;
 
