@@ -550,6 +550,33 @@ __device__ __forceinline__ void store_partial(double acc, int blk, double *parti
     if (threadIdx.x < R) partials[(int64_t)blk * R + threadIdx.x] = t;
 }
 
+// Per-workgroup partials of the paired-lane kernels (R >= kPairR, R/2 lanes
+// per row, BS threads): lane w holds the sums of right-hand sides 2w and
+// 2w+1; partials are written to partials[blk * R + rhs] like store_partial's.
+template <int R, int BS = kBlock>
+__device__ __forceinline__ void store_partial2(double acc0, double acc1, int blk, double *partials) {
+    constexpr int LN = pass_lanes(R);
+    __shared__ double sh[(BS / 64) * R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= LN; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off, 64);
+        acc1 += __shfl_xor(acc1, off, 64);
+    }
+    __syncthreads();
+    if (lane < LN) {
+        sh[wv * R + 2 * lane] = acc0;
+        sh[wv * R + 2 * lane + 1] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double t = sh[threadIdx.x];
+#pragma unroll
+        for (int k = 1; k < BS / 64; ++k) t += sh[k * R + threadIdx.x];
+        partials[(int64_t)blk * R + threadIdx.x] = t;
+    }
+}
+
 // One colour of the coloured Gauss-Seidel pass (Listing 3 of the paper, the
 // masked product and the update fused).  Rows of one colour are independent,
 // so the update is done in place: a row reads only other colours and itself.
@@ -640,11 +667,13 @@ __device__ __forceinline__ void st_lanes(T *p, const T (&v)[N]) {
 // values move as 16-byte pairs, which halves the per-lane address work of a
 // pass whose texture unit is otherwise its bottleneck.  Each right-hand
 // side's arithmetic is exactly pass_row's.
-template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, class SB, bool TWICE>
+// DOT: rz[u] = r times the stored z of right-hand side 2w+u (for <r, z>).
+template <typename T, int R, uint32_t SKIP, bool NT, int MODE, int CF, class SB, bool TWICE, bool DOT = false>
 __device__ __forceinline__ void pass_row2(int64_t n, const int32_t *__restrict__ col,
                                           const int8_t *__restrict__ dcol, const SB &sb, const T *__restrict__ r,
                                           T *z, int64_t i, int w, int64_t inj_base, T *__restrict__ coarse,
-                                          const int32_t *__restrict__ inj_coarse, const T *vs, int vstride) {
+                                          const int32_t *__restrict__ inj_coarse, const T *vs, int vstride,
+                                          double (&rz)[2]) {
     typedef T V2 __attribute__((ext_vector_type(2)));
     const int64_t o = i * R + 2 * w;
     const V2 rv = *(const V2 *)(r + o);
@@ -673,9 +702,17 @@ __device__ __forceinline__ void pass_row2(int64_t n, const int32_t *__restrict__
         z2.x = gs_again(a, x0, rv.x, zn.x);
         z2.y = gs_again(a, x1, rv.y, zn.y);
         *(V2 *)(z + o) = z2;
+        if (DOT) {
+            rz[0] = (double)rv.x * (double)z2.x;
+            rz[1] = (double)rv.y * (double)z2.y;
+        }
         return;
     }
     *(V2 *)(z + o) = zn;
+    if (DOT) {
+        rz[0] = (double)rv.x * (double)zn.x;
+        rz[1] = (double)rv.y * (double)zn.y;
+    }
     if (MODE == 1) {
         xv[kCentre] = zn;
         V2 rc;
@@ -730,12 +767,14 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
             if (all) return;
         }
         stage_values<T, SKIP, NT, RW, pass_block(NT)>(val, row0, count, sv);
-        if (rl >= count) return;
+        double rz[2] = {0.0, 0.0};
         // several grids: a lane whose two systems have both converged stores
         // nothing (z is internal: a converged system's z is never used again)
-        if (tab && done && done[grid * R + 2 * w] && done[grid * R + 2 * w + 1]) return;
-        pass_row2<T, R, SKIP, NT, MODE, CF, Base27, TWICE>(n, col, dcol, sb, r, z, row0 + rl, w, row_base, coarse,
-                                                       inj_coarse, sv + rl, RW);
+        if (rl < count && !(tab && done && done[grid * R + 2 * w] && done[grid * R + 2 * w + 1]))
+            pass_row2<T, R, SKIP, NT, MODE, CF, Base27, TWICE, DOT>(n, col, dcol, sb, r, z, row0 + rl, w, row_base,
+                                                                    coarse, inj_coarse, sv + rl, RW, rz);
+        // DOT (one grid, no table): every thread takes part in the sum
+        if constexpr (DOT) store_partial2<R, pass_block(NT)>(rz[0], rz[1], b, rzp);
         return;
     }
     const int rl = threadIdx.x / R, v = threadIdx.x % R;
@@ -1601,33 +1640,6 @@ __device__ __forceinline__ Seg vec_seg(const Seg *__restrict__ tab, int blk, int
     return e;
 }
 
-// Per-workgroup partials of the paired-lane kernels (R >= kPairR, R/2 lanes
-// per row): lane w holds the sums of right-hand sides 2w and 2w+1; partials
-// are written to partials[blk * R + rhs] like store_partial's.
-template <int R>
-__device__ __forceinline__ void store_partial2(double acc0, double acc1, int blk, double *partials) {
-    constexpr int LN = pass_lanes(R);
-    __shared__ double sh[(kBlock / 64) * R];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off >= LN; off >>= 1) {
-        acc0 += __shfl_xor(acc0, off, 64);
-        acc1 += __shfl_xor(acc1, off, 64);
-    }
-    __syncthreads();
-    if (lane < LN) {
-        sh[wv * R + 2 * lane] = acc0;
-        sh[wv * R + 2 * lane + 1] = acc1;
-    }
-    __syncthreads();
-    if (threadIdx.x < R) {
-        double t = sh[threadIdx.x];
-#pragma unroll
-        for (int k = 1; k < kBlock / 64; ++k) t += sh[k * R + threadIdx.x];
-        partials[(int64_t)blk * R + threadIdx.x] = t;
-    }
-}
-
 // sum_j a_ij x_j of row i for right-hand sides 2w and 2w+1 (values staged in
 // LDS), each in row_sum's slot order
 template <int R, int CF, class SB>
@@ -2083,8 +2095,8 @@ static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hi
     const double *parts = P->sc.partials;
     // partials of one grid: the workgroups of the producing kernel(s)
     int nblk = table == 2 ? (int)P->rz_off[8] : P->n_red[table];
-    if (P->fold && table < 2) {
-        MG_DISPATCH_R(P->R, (k_fold<RR><<<kFoldBlocks, kBlock, 0, s>>>(P->sc.partials, P->n_red[table], P->fold)));
+    if (P->fold) {
+        MG_DISPATCH_R(P->R, (k_fold<RR><<<kFoldBlocks, kBlock, 0, s>>>(P->sc.partials, nblk, P->fold)));
         parts = P->fold;
         nblk = kFoldBlocks;
     }

@@ -605,12 +605,12 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             ST_TRY(upload(&P->red_tab[t], tab, s));
             ST_TRY(upload(&P->red_gb[t], gb, s));
         }
-        // <r,z> fused into the level-0 post-smoother: one grid and one
-        // right-hand side (several would multiply the partials the single
-        // finalize workgroup sums), FP64 V-cycle (whose level-0 z is the CG
+        // <r,z> fused into the level-0 post-smoother: one grid (several
+        // would need per-grid partial ranges; with R > 1 the fold kernel
+        // pre-sums the partials), FP64 V-cycle (whose level-0 z is the CG
         // z), the standard sweep with the double pass (the last update of
         // colour c-1 is that pass)
-        P->fuse_rz = G == 1 && R == 1 && P->mg_dtype == MGPCG_FP64 && L0.ncol == 8 &&
+        P->fuse_rz = G == 1 && P->mg_dtype == MGPCG_FP64 && L0.ncol == 8 &&
                      P->smoother == MGPCG_SMOOTHER_COLOURED;
         if (P->fuse_rz) {
             // the partials buffer serves either level-0 workgroup size
