@@ -29,43 +29,6 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * per + (x < rem ? x : rem) + q;
 }
 
-// Workgroup order of a one-grid colour pass with several right-hand sides.
-// A point then carries 8R bytes, and the rows an XCD has in flight (about a
-// half-plane of the colour in row order) gather from three fine planes, more
-// than its L2 holds, so neighbour values are fetched again.  Here each XCD's
-// z-slab of the colour is visited in y-blocks of `yb` half-lines, all of the
-// slab's half-planes per block, so the rows in flight form a compact box.
-// Rows of one colour are independent: the order changes no result.
-struct PassGeo {
-    int32_t hxq = 0;    // workgroups per half-line (0: row order)
-    int32_t hy = 0;     // half-lines per half-plane
-    int32_t zs = 0;     // half-planes per slab (one slab per XCD)
-    int32_t yb = 0;     // half-lines per y-block (divides hy)
-    int32_t split = 0;  // two colours of equal extents (the fused zero-start
-                        // pass): the first workgroup of the second (0: one)
-};
-
-// row block (in units of the pass's rows per workgroup, from the first row of
-// the range) of logical workgroup p
-__device__ __forceinline__ int64_t geo_block(int p, const PassGeo &g) {
-    if (g.hxq == 0) return p;
-    int base = 0;
-    if (g.split && p >= g.split) {
-        base = g.split;
-        p -= g.split;
-    }
-    const int line = g.hxq, blk = g.yb * line, ybk = g.zs * blk, slab = g.hy * g.zs * line;
-    const int sl = p / slab;
-    int q = p - sl * slab;
-    const int y0 = q / ybk;
-    q -= y0 * ybk;
-    const int jz = q / blk;
-    q -= jz * blk;
-    const int jy = q / line;
-    const int jq = q - jy * line;
-    return base + ((int64_t)(sl * g.zs + jz) * g.hy + (int64_t)y0 * g.yb + jy) * line + jq;
-}
-
 __device__ __forceinline__ double softplus_d(double t) {
     return fmax(t, 0.0) + log1p(exp(-fabs(t)));
 }
@@ -732,8 +695,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
                                                  const Seg *__restrict__ tab, int64_t row_base,
                                                  int64_t row_end, const int *__restrict__ done,
                                                  T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
-                                                 double *__restrict__ rzp, const int32_t *__restrict__ gbase,
-                                                 const PassGeo geo) {
+                                                 double *__restrict__ rzp, const int32_t *__restrict__ gbase) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
@@ -750,7 +712,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
             for (int t = 0; t < kW; ++t) sb.v[t] = gb[t];
         }
     } else {
-        row0 = row_base + geo_block(b, geo) * pass_rows(NT, R);
+        row0 = row_base + (int64_t)b * pass_rows(NT, R);
         count = row_end - row0;
         grid = 0;
     }
@@ -823,7 +785,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
                                                       const T *__restrict__ r, T *__restrict__ z,
                                                       const Seg *__restrict__ tab, int64_t coff0, int64_t coff1,
                                                       int64_t coff2, const int *__restrict__ done,
-                                                      const int32_t *__restrict__ gbase, const PassGeo geo) {
+                                                      const int32_t *__restrict__ gbase) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
@@ -839,7 +801,7 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
             for (int t = 0; t < kW; ++t) sb1.v[t] = gb[t];
         }
     } else {
-        row0 = coff0 + geo_block(b, geo) * pass_rows(NT, R);
+        row0 = coff0 + (int64_t)b * pass_rows(NT, R);
         count = coff2 - row0;
         grid = 0;
     }
@@ -906,11 +868,11 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
 template <typename T, int R, bool NT, int CF>
 static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T *val, const int32_t *col,
                     const int8_t *dcol, const Base27 &sb, const T *r, T *z, const Seg *tab, int64_t rb,
-                    int64_t re, const int *done, const int32_t *gb, const PassGeo &geo) {
+                    int64_t re, const int *done, const int32_t *gb) {
 #define MG_ZS_CASE(K, O)                                                                              \
     case K + 8 * O:                                                                                   \
         k_pass<T, R, zs_mask(K, O), NT, 0, CF><<<cnt, pass_block(NT), 0, s>>>(n, val, col, dcol, sb, r, z, tab, rb, re, \
-                                                                      done, nullptr, nullptr, nullptr, gb, geo); \
+                                                                      done, nullptr, nullptr, nullptr, gb); \
         break;
     switch (k + 8 * order) {
         MG_ZS_CASE(0, 0) MG_ZS_CASE(1, 0) MG_ZS_CASE(2, 0) MG_ZS_CASE(3, 0)
@@ -925,22 +887,6 @@ static void pass_zs(int k, int order, int cnt, hipStream_t s, int64_t n, const T
 uint32_t standard_zs_mask(int k, int order) { return zs_mask(k, order); }
 static_assert(zs_mask(7, 0) == (1u << kCentre) && zs_mask(7, 1) == (1u << kCentre),
               "the last colour of a zero-start sweep reads every neighbour");
-
-// Workgroup order of a one-grid pass over colour k whose rows split into
-// nslab equal z-slabs (see PassGeo); row order when it does not apply.
-static PassGeo pass_geo(const mgpcg_problem *P, const Level &L, int k, int nslab) {
-    PassGeo g;
-    if (P->G != 1 || P->R < 2 || P->pass_yblock <= 0) return g;
-    const int rows = pass_rows(L.stream_nt, P->R);
-    const int32_t *h = L.grids[0].half[k];
-    const int yb = std::min<int>(P->pass_yblock, h[1]);
-    if (rows <= 0 || yb <= 0 || h[0] % rows || h[2] % nslab || h[1] % yb) return g;
-    g.hxq = h[0] / rows;
-    g.hy = h[1];
-    g.zs = h[2] / nslab;
-    g.yb = yb;
-    return g;
-}
 
 template <typename T>
 hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const T *val, const T *r, T *z,
@@ -973,7 +919,6 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     const int32_t *ic = L.inj_coarse;
     Base27 sb;
     for (int t = 0; t < kW; ++t) sb.v[t] = L.cf ? L.dbase_host[k * kW + t] : 0;
-    const PassGeo geo = pass_geo(P, L, k, kXcd);
     if (mode == kPassZeroStart01) {
         if (k != 0 || !L.zs_std || L.ncol != 8 || (R != 1 && R != 16)) return hipErrorInvalidValue;
         int cnt01;
@@ -987,22 +932,13 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         }
         Base27 sb1;
         for (int t = 0; t < kW; ++t) sb1.v[t] = L.cf ? L.dbase_host[1 * kW + t] : 0;
-        // colours 0 and 1 each over half of the XCDs
-        PassGeo geo01 = pass_geo(P, L, 0, kXcd / 2);
-        if (geo01.hxq) {
-            const int32_t *h0 = L.grids[0].half[0], *h1 = L.grids[0].half[1];
-            if (h0[0] == h1[0] && h0[1] == h1[1] && h0[2] == h1[2])
-                geo01.split = geo01.hxq * h0[1] * h0[2];
-            else
-                geo01 = PassGeo{};
-        }
 #define MG_ZS01(RR, NT, CF)                                                                             \
     if (P->colour_order)                                                                               \
         k_pass_zs01<T, RR, NT, CF, 1><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
-                                                            L.coff[0], L.coff[1], L.coff[2], done, gb, geo01); \
+                                                            L.coff[0], L.coff[1], L.coff[2], done, gb);  \
     else                                                                                               \
         k_pass_zs01<T, RR, NT, CF, 0><<<cnt01, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb1, r, z, tab01,      \
-                                                            L.coff[0], L.coff[1], L.coff[2], done, gb, geo01);
+                                                            L.coff[0], L.coff[1], L.coff[2], done, gb);
 #define MG_ZS01_R(NT, CF)                                                                               \
     if (R == 1) { MG_ZS01(1, NT, CF) } else { MG_ZS01(16, NT, CF) }
         if (L.stream_nt) {
@@ -1022,10 +958,10 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (rzp && SKIPM == 0u) {                                                                          \
         if constexpr (sizeof(T) == 8)                                                                  \
             MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true, true><<<cnt, pass_block(NT), 0, s>>>(  \
-                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp, gb, geo))); \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, rzp, gb))); \
     } else {                                                                                           \
         MG_DISPATCH_R(R, (k_pass<T, RR, SKIPM, NT, 0, CF, true><<<cnt, pass_block(NT), 0, s>>>(            \
-                             L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr, gb, geo))); \
+                             L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, nullptr, nullptr, nullptr, gb))); \
     }
 #define MG_TWICE_MODE(SKIPM)                                                                            \
     if (L.stream_nt) {                                                                                 \
@@ -1046,8 +982,8 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
         if (!L.zs_std || (R != 1 && R != 16)) return hipErrorInvalidValue;
         const int ord = P->colour_order;
 #define MG_ZS_LAUNCH(NT, CF)                                                                           \
-    if (R == 1) pass_zs<T, 1, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb, geo); \
-    else pass_zs<T, 16, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb, geo);
+    if (R == 1) pass_zs<T, 1, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb); \
+    else pass_zs<T, 16, NT, CF>(k, ord, cnt, s, L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, gb);
         if (L.stream_nt) {
             if (L.cf == 2) { MG_ZS_LAUNCH(true, 2) } else if (L.cf == 1) { MG_ZS_LAUNCH(true, 1) } else { MG_ZS_LAUNCH(true, 0) }
         } else {
@@ -1060,11 +996,11 @@ hipError_t launch_pass(const mgpcg_problem *P, int level, int k, int mode, const
     if (M == 0 && rzp) {                                                                               \
         if constexpr (sizeof(T) == 8)                                                                  \
             MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, 0, CF, false, true><<<cnt, pass_block(NT), 0, s>>>(    \
-                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp, gb, geo))); \
+                                 L.n, val, L.col, L.dcol, sb, r, z, tab, rb, re, done, coarse, ic, rzp, gb))); \
     } else {                                                                                           \
         MG_DISPATCH_R(R, (k_pass<T, RR, 0u, NT, M, CF><<<cnt, pass_block(NT), 0, s>>>(L.n, val, L.col, L.dcol, sb, \
                                                                           r, z, tab, rb, re, done, coarse, ic, \
-                                                                          nullptr, gb, geo)));    \
+                                                                          nullptr, gb)));         \
     }
 #define MG_PASS_MODE(M)                                                                                \
     if (L.stream_nt) {                                                                                 \

@@ -232,14 +232,10 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             Lv.ncol = std::max(Lv.ncol, C.ncol);
             for (int k = 0; k < 8; ++k) {
                 lg.seg_len[k] = 0;
-                lg.half[k][0] = lg.half[k][1] = lg.half[k][2] = 0;
                 if (k < C.ncol) {
                     int b[3];
                     C.parity(k, b);
-                    lg.half[k][0] = (int32_t)half_count(lg.nx, b[0]);
-                    lg.half[k][1] = (int32_t)half_count(lg.ny, b[1]);
-                    lg.half[k][2] = (int32_t)half_count(lg.nz, b[2]);
-                    lg.seg_len[k] = (int64_t)lg.half[k][0] * lg.half[k][1] * lg.half[k][2];
+                    lg.seg_len[k] = half_count(lg.nx, b[0]) * half_count(lg.ny, b[1]) * half_count(lg.nz, b[2]);
                 }
             }
             lg.inj_colour = C.colour(0, 0, 0);
@@ -744,11 +740,16 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
         if (const char *env = getenv("MGPCG_TAIL_BYTES")) tail_bytes = atoll(env);  // tuning override
         const Level &Lt = P->lev[L - 1];
         const int64_t need = Lt.n * 2 * (fp32 ? 4 : 8);
-        bool fits = true;
-        for (int k = 0; k < Lt.ncol; ++k) fits = fits && Lt.coff[k + 1] - Lt.coff[k] <= kTailBlock;
+        int64_t widest = 0;
+        for (int k = 0; k < Lt.ncol; ++k) widest = std::max<int64_t>(widest, Lt.coff[k + 1] - Lt.coff[k]);
         P->tail_ok = L >= 2 && R == 1 && P->sweeps == 1 && Lt.zs_std && Lt.ncol == 8 && need <= tail_bytes &&
-                     need <= (64 << 10) && fits && (G == 1 || Lt.cf == 0);
+                     need <= (64 << 10) && widest <= kTailBlock && (G == 1 || Lt.cf == 0);
         P->tail_lw = P->tail_ok ? L - 1 : L;
+        // default: the tail only while its colours fill at most half the
+        // workgroup (measured: at 128^3, 512 rows per colour, the 15 pass
+        // kernels are 5 us per CG iteration faster; at 96^3, 216 rows, the
+        // tail is 2 us faster); the schedule can choose either
+        P->tail_on = widest <= kTailBlock / 2 ? 1 : 0;
     }
     HIP_TRY(hipHostMalloc((void **)&P->pinned_ndone, sizeof(int) * mgpcg_problem::kCheckRing, hipHostMallocDefault));
     for (int j = 0; j < mgpcg_problem::kCheckRing; ++j)
@@ -1306,8 +1307,6 @@ mgpcg_status mgpcg_create(const mgpcg_config *cfg, hipStream_t stream, mgpcg_pro
     P->dims0.assign(cfg->dims, cfg->dims + 3 * cfg->ngrids);
     // tuning and test override: 0 int32 columns, 1 at most int8 deltas, 2 (default) implied columns allowed
     if (const char *env = getenv("MGPCG_DELTA_COLS")) P->col_format = std::min(2, std::max(0, atoi(env)));
-    // tuning override: y-block of the multi-rhs colour passes (0: row order)
-    if (const char *env = getenv("MGPCG_PASS_YBLOCK")) P->pass_yblock = std::max(0, atoi(env));
     mgpcg_status st = build_hierarchy(P, cfg->theta, stream);
     if (st != MGPCG_OK) {
         std::string msg = g_err;

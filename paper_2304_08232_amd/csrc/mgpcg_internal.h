@@ -88,7 +88,6 @@ struct LevelGrid {  // one grid at one level
     int64_t nat_off;     // first row of this grid in the natural packed order
     int64_t seg_off[8];  // first internal row of (colour k, this grid)
     int64_t seg_len[8];  // rows of (colour k, this grid)
-    int32_t half[8][3];  // (x, y, z) extents of colour k's points: its rows run z, y, x (x fastest)
     int inj_colour;      // colour holding the injection points (2jx,2jy,2jz)
 };
 
@@ -209,10 +208,6 @@ struct mgpcg_problem {
     int lex_run_rows = 256;  // sequential smoother: largest wavefront a single-workgroup run takes
     // most compact column format allowed (Level::cf), 2 by default
     int col_format = 2;
-    // one grid with several right-hand sides: the colour passes visit their
-    // rows in y-blocks of this many half-lines within each XCD's z-slab (0:
-    // in row order)
-    int pass_yblock = 0;
     std::vector<int> dims0;  // 3*G, level 0
     std::vector<mg::Level> lev;
 
