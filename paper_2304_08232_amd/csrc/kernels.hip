@@ -29,6 +29,21 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * per + (x < rem ? x : rem) + q;
 }
 
+// Kernel arguments arrive by scalar loads, which complete out of order, so
+// each use of one waits for every scalar load issued before it.  Left alone,
+// the compiler issues the arguments in the groups the code needs next, with a
+// wait after each group: several round trips before a kernel's first memory
+// load.  Naming the arguments the first loads need in one empty asm statement
+// at the top makes it issue all of them before the first wait.  (Naming
+// every argument instead was slower: the compiler then reloads some of them
+// one word at a time.)
+#define MG_ARGS_FIRST(...) asm volatile("" ::__VA_ARGS__)
+// the upper column bases (the lower 16 come in one wide load anyway)
+#define MG_BASES_FIRST(B)                                                                            \
+    asm volatile("" ::"s"((B).v[16]), "s"((B).v[17]), "s"((B).v[18]), "s"((B).v[19]), "s"((B).v[20]), \
+                 "s"((B).v[21]), "s"((B).v[22]), "s"((B).v[23]), "s"((B).v[24]), "s"((B).v[25]),      \
+                 "s"((B).v[26]))
+
 __device__ __forceinline__ double softplus_d(double t) {
     return fmax(t, 0.0) + log1p(exp(-fabs(t)));
 }
@@ -697,6 +712,9 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass(int64_t n, const T *__r
                                                  T *__restrict__ coarse, const int32_t *__restrict__ inj_coarse,
                                                  double *__restrict__ rzp, const int32_t *__restrict__ gbase) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
+    // every argument the first loads need, in one batch (see MG_ARGS_FIRST)
+    MG_ARGS_FIRST("s"(n), "s"(val), "s"(r), "s"(z), "s"(tab), "s"(row_base), "s"(row_end), "s"(done));
+    if constexpr (CF != 0) MG_BASES_FIRST(sb_arg);
     int64_t row0, count;
     int grid;
     Base27 sb = sb_arg;
@@ -786,6 +804,9 @@ __global__ __launch_bounds__(pass_block(NT)) void k_pass_zs01(int64_t n, const T
                                                       const Seg *__restrict__ tab, int64_t coff0, int64_t coff1,
                                                       int64_t coff2, const int *__restrict__ done,
                                                       const int32_t *__restrict__ gbase) {
+    MG_ARGS_FIRST("s"(n), "s"(val), "s"(r), "s"(z), "s"(tab), "s"(coff0), "s"(coff1), "s"(coff2), "s"(done),
+                  "s"(gridDim.x));
+    if constexpr (CF != 0) MG_BASES_FIRST(sb_arg);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     int64_t row0, count;
     int grid;
@@ -1734,6 +1755,8 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void k_update_p(const double *__restrict__ z, double *__restrict__ p,
                                                      double *__restrict__ x, const Seg *__restrict__ tab,
                                                      int64_t nrows, Scalars sc) {
+    MG_ARGS_FIRST("s"(z), "s"(p), "s"(x), "s"(tab), "s"(nrows), "s"(sc.beta), "s"(sc.apend), "s"(sc.done),
+                  "s"(gridDim.x));
     const Seg e = vec_seg(tab, xcd_remap(blockIdx.x, gridDim.x), nrows, kVecRows * kBlock / R);
     const int v = threadIdx.x % R;
     const int sys = e.grid * R + v;
@@ -1788,6 +1811,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
                                                     const double *__restrict__ p, double *__restrict__ q,
                                                     const Seg *__restrict__ tab, double *__restrict__ partials,
                                                     const int *__restrict__ done, int spc) {
+    // (its arguments are left to the compiler: naming them up front moved the
+    // table-entry load to the vector unit and cost 9 us per CG iteration)
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t first = (int64_t)blk * (R == 1 ? 1 : spc);
     // the entries of a workgroup belong to one grid
@@ -1867,6 +1892,8 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void k_update_r(double *__restrict__ r, const double *__restrict__ q,
                                                      const Seg *__restrict__ tab, int64_t nrows,
                                                      double *__restrict__ partials, Scalars sc) {
+    MG_ARGS_FIRST("s"(r), "s"(q), "s"(tab), "s"(nrows), "s"(partials), "s"(sc.alpha), "s"(sc.done),
+                  "s"(gridDim.x));
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const Seg e = vec_seg(tab, blk, nrows, kVecRows * kBlock / R);
     if (tab && grid_done<R>(sc.done, e.grid)) return;
@@ -1918,6 +1945,7 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
     // take one memory round trip.  A thread's loads are straight-line (a
     // load past the end rereads the last partial and adds 0 instead), up to
     // 32 of them per round trip.
+    MG_ARGS_FIRST("s"(gb), "s"(nblk), "s"(partials), "s"(sc.done), "s"(sc.iter));
     const int b0 = gb ? gb[g] : 0, b1 = gb ? gb[g + 1] : nblk;
     constexpr int kStep = FB / R, kU = 32;  // 64 would spill at 1024 threads
     double t[kU];
