@@ -1931,28 +1931,24 @@ __global__ __launch_bounds__(kBlock) void k_update_r(double *__restrict__ r, con
 // per system would need R times as many round trips, so R > 1 uses 1024.
 constexpr int fin_block(int R) { return R == 1 ? kBlock : 1024; }
 
-template <int R, int KIND>
-__global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict__ gb, int nblk,
-                                                           const double *__restrict__ partials, Scalars sc,
-                                                           double *__restrict__ hist, int hist_cap, double tol) {
+// The body of k_finalize with KU straight-line partial loads per thread and
+// round trip (a load past the end rereads the last partial and adds 0):
+// 32 for the long ranges of one workgroup per producing block, 4 for folded
+// partials, whose few values would otherwise cost 28 redundant loads a
+// thread.
+template <int R, int KIND, int KU>
+__device__ __forceinline__ void finalize_body(int g, int b0, int b1, const double *__restrict__ partials,
+                                              const Scalars &sc, double *__restrict__ hist, int hist_cap,
+                                              double tol) {
     constexpr int FB = fin_block(R);
     __shared__ double sh[(FB / 64) * R];
-    const int g = blockIdx.x;
     const int v = threadIdx.x % R;
-    // One grid (gb == NULL): the partials are [0, nblk), so their loads wait
-    // for no table load.  The convergence flags and the scalars of the
-    // update are loaded after the partials are on their way, so that both
-    // take one memory round trip.  A thread's loads are straight-line (a
-    // load past the end rereads the last partial and adds 0 instead), up to
-    // 32 of them per round trip.
-    MG_ARGS_FIRST("s"(gb), "s"(nblk), "s"(partials), "s"(sc.done), "s"(sc.iter));
-    const int b0 = gb ? gb[g] : 0, b1 = gb ? gb[g + 1] : nblk;
-    constexpr int kStep = FB / R, kU = 32;  // 64 would spill at 1024 threads
-    double t[kU];
+    constexpr int kStep = FB / R;
+    double t[KU];
     int b = b0 + threadIdx.x / R;
     if (b1 > b0) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
             const int bb = b + u * kStep;
             t[u] = partials[(int64_t)(bb < b1 ? bb : b1 - 1) * R + v];
         }
@@ -1972,11 +1968,11 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
     double s = 0.0;
     while (b < b1) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) s += (b + u * kStep < b1) ? t[u] : 0.0;
-        b += kU * kStep;
+        for (int u = 0; u < KU; ++u) s += (b + u * kStep < b1) ? t[u] : 0.0;
+        b += KU * kStep;
         if (b < b1) {
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
+            for (int u = 0; u < KU; ++u) {
                 const int bb = b + u * kStep;
                 t[u] = partials[(int64_t)(bb < b1 ? bb : b1 - 1) * R + v];
             }
@@ -2024,6 +2020,23 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
             atomicAdd(sc.ndone, 1);
         }
     }
+}
+
+// One grid (gb == NULL): the partials are [0, nblk), so their loads wait for
+// no table load.  The convergence flags and the scalars of the update are
+// loaded after the partials are on their way, so that both take one memory
+// round trip.
+template <int R, int KIND>
+__global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict__ gb, int nblk,
+                                                           const double *__restrict__ partials, Scalars sc,
+                                                           double *__restrict__ hist, int hist_cap, double tol) {
+    MG_ARGS_FIRST("s"(gb), "s"(nblk), "s"(partials), "s"(sc.done), "s"(sc.iter));
+    const int g = blockIdx.x;
+    const int b0 = gb ? gb[g] : 0, b1 = gb ? gb[g + 1] : nblk;
+    if (b1 - b0 <= 4 * (fin_block(R) / R))
+        finalize_body<R, KIND, 4>(g, b0, b1, partials, sc, hist, hist_cap, tol);
+    else
+        finalize_body<R, KIND, 32>(g, b0, b1, partials, sc, hist, hist_cap, tol);  // 64 would spill at 1024 threads
 }
 
 // One grid with R > 1: the per-workgroup partials of a reduction (nblk * R

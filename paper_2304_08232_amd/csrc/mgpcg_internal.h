@@ -30,7 +30,7 @@ constexpr int kW = 27;        // ELL width (3x3x3 stencil)
 constexpr int kCentre = 13;   // slot of the diagonal
 constexpr int kBlock = 256;   // threads per workgroup
 constexpr int kVecRows = 4;   // rows per thread in the CG vector kernels
-constexpr int kFoldBlocks = 64;  // workgroups that pre-sum the CG partials (one grid, R > 1)
+constexpr int kFoldBlocks = 256;  // workgroups that pre-sum the CG partials (one grid, R > 1)
 constexpr int kXcdCount = 8;     // XCDs of the part; workgroup b is dispatched to XCD b % 8
 // Workgroup size of a colour pass: 256 threads on streamed (large) levels;
 // one wavefront on cache-resident levels, whose passes are latency-bound, so
