@@ -216,12 +216,12 @@ __device__ __forceinline__ void load_row(const T *__restrict__ val, const int32_
 // column order), skipping padding slots (value 0).  Slots whose bit is set in
 // the compile-time SKIP mask are left out entirely (their x is known to be
 // zero); the diagonal value is always loaded and returned in d.
-template <typename T, int R, uint32_t SKIP, bool NT, int CF, bool VS = false>
+template <typename T, int R, uint32_t SKIP, bool NT, int CF, bool VS = false, class SB = const int32_t *>
 __device__ __forceinline__ T row_sum(const T *__restrict__ val, const int32_t *__restrict__ col,
-                                     const int8_t *__restrict__ dcol, const int32_t *__restrict__ sb, int64_t n,
+                                     const int8_t *__restrict__ dcol, const SB &sb, int64_t n,
                                      int64_t i, const T *x, int v, T &d, const T *vs = nullptr, int vstride = 0) {
     T a[kW], xv[kW];
-    load_row<T, R, SKIP, NT, CF, decltype(sb), VS>(val, col, dcol, sb, n, i, x, v, a, xv, vs, vstride);
+    load_row<T, R, SKIP, NT, CF, SB, VS>(val, col, dcol, sb, n, i, x, v, a, xv, vs, vstride);
     d = a[kCentre];
     T acc = 0;
 #pragma unroll
@@ -1435,19 +1435,31 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int64_t n, const T *__restr
                                                      const int8_t *__restrict__ dcol,
                                                      const int32_t *__restrict__ dbase,
                                                      const int32_t *__restrict__ grow, CoffTable ct,
+                                                     const Base27 sb_inj,
                                                      const T *__restrict__ r, const T *__restrict__ z,
                                                      T *__restrict__ rc,
                                                      const int32_t *__restrict__ inj_fine,
                                                      const int32_t *__restrict__ inj_coarse,
                                                      int64_t n_inj) {
+    MG_ARGS_FIRST("s"(n), "s"(val), "s"(grow), "s"(r), "s"(z), "s"(rc), "s"(inj_fine), "s"(inj_coarse), "s"(n_inj),
+                  "s"(gridDim.x));
+    if constexpr (CF != 0) MG_BASES_FIRST(sb_inj);
     int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (gid >= n_inj * R) return;
     int64_t t = gid / R;
     int v = (int)(gid % R);
     int64_t i = inj_fine[t];
     T d;
-    const int32_t *sb = CF ? dbase + ((grow ? grow[i] : 0) * 8 + colour_of(ct.coff, ct.ncol, i)) * kW : nullptr;
-    const T acc = row_sum<T, R, 0u, NT, CF>(val, col, dcol, sb, n, i, z, v, d);
+    T acc;
+    if (CF && grow) {
+        // several grids: the bases of the row's grid and colour, per lane
+        const int32_t *sb = dbase + (grow[i] * 8 + colour_of(ct.coff, ct.ncol, i)) * kW;
+        acc = row_sum<T, R, 0u, NT, CF>(val, col, dcol, sb, n, i, z, v, d);
+    } else {
+        // one grid: every injection point has the same colour, whose bases
+        // come with the arguments (no dependent table load)
+        acc = row_sum<T, R, 0u, NT, CF>(val, col, dcol, sb_inj, n, i, z, v, d);
+    }
     rc[(int64_t)inj_coarse[t] * R + v] = r[i * R + v] - acc;
 }
 
@@ -1458,9 +1470,12 @@ hipError_t launch_restrict(const mgpcg_problem *P, int level, const T *val, cons
     int64_t work = L.n_inj * P->R;
     if (work == 0) return hipSuccess;
     const CoffTable ct = coff_table(L);
+    Base27 sb_inj;  // one grid: the bases of the injection colour
+    const int kinj = P->G == 1 ? L.grids[0].inj_colour : 0;
+    for (int t = 0; t < kW; ++t) sb_inj.v[t] = L.cf ? L.dbase_host[kinj * kW + t] : 0;
 #define MG_RESTRICT(NT, CF)                                                                             \
     MG_DISPATCH_R(P->R, (k_restrict<T, RR, NT, CF><<<nblocks(work), kBlock, 0, s>>>(                    \
-                            L.n, val, L.col, L.dcol, L.dbase, L.grid_of_row, ct, r, z, rc, L.inj_fine,          \
+                            L.n, val, L.col, L.dcol, L.dbase, L.grid_of_row, ct, sb_inj, r, z, rc, L.inj_fine,  \
                             L.inj_coarse, L.n_inj)));
     if (L.stream_nt) {
         if (L.cf == 2) { MG_RESTRICT(true, 2) } else if (L.cf == 1) { MG_RESTRICT(true, 1) } else { MG_RESTRICT(true, 0) }
@@ -1481,6 +1496,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const T *__restrict__ zc, T 
                                                     const int32_t *__restrict__ inj_fine,
                                                     const int32_t *__restrict__ inj_coarse,
                                                     int64_t n_inj) {
+    MG_ARGS_FIRST("s"(zc), "s"(z), "s"(inj_fine), "s"(inj_coarse), "s"(n_inj), "s"(gridDim.x));
     int64_t gid = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (gid >= n_inj * R) return;
     int64_t t = gid / R;
@@ -1507,11 +1523,13 @@ template hipError_t launch_prolong<float>(const mgpcg_problem *, int, const floa
 
 __global__ __launch_bounds__(kBlock) void k_cast_d2f(const double *__restrict__ a, float *__restrict__ b,
                                                      int64_t n) {
+    MG_ARGS_FIRST("s"(a), "s"(b), "s"(n));
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
 }
 __global__ __launch_bounds__(kBlock) void k_cast_f2d(const float *__restrict__ a, double *__restrict__ b,
                                                      int64_t n) {
+    MG_ARGS_FIRST("s"(a), "s"(b), "s"(n));
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) b[i] = (double)a[i];
 }
@@ -2046,6 +2064,7 @@ __global__ __launch_bounds__(fin_block(R)) void k_finalize(const int *__restrict
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_fold(const double *__restrict__ partials, int nblk,
                                                  double *__restrict__ fold) {
+    MG_ARGS_FIRST("s"(partials), "s"(nblk), "s"(fold));
     __shared__ double sh[(kBlock / 64) * R];
     const int w = blockIdx.x;
     const int b0 = (int)((int64_t)nblk * w / kFoldBlocks), b1 = (int)((int64_t)nblk * (w + 1) / kFoldBlocks);
