@@ -147,6 +147,22 @@ def time_to_tol(torch, prob, b, tol, max_iters=1000, reps=3):
     return best, out
 
 
+def queue_spin(torch, stream, ms=30.0):
+    """Queue a spin kernel of about `ms` on the stream, so that the launches
+    queued after it run back to back: otherwise a host slower than one launch
+    per kernel duration would add its gaps to the measured time.  The spin is
+    sized from a timed 2^20-cycle spin, far more than the host needs to
+    queue, and bounded to 1e6..1e8 cycles (at most 1 s even at a 100 MHz
+    counter)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    torch.cuda._sleep(1 << 20)
+    e1.record(stream)
+    e1.synchronize()
+    cycles_per_ms = (1 << 20) / max(e0.elapsed_time(e1), 1e-3)
+    torch.cuda._sleep(int(min(max(ms * cycles_per_ms, 1e6), 1e8)))
+
+
 def dominant_kernel(torch, mg, prob, reps=40):
     """Average duration of the level-0 colour pass kernel (k_pass, plain mode)
     from HIP events recorded on the stream the library launches it on: the
@@ -158,17 +174,7 @@ def dominant_kernel(torch, mg, prob, reps=40):
     for _ in range(3):  # warm-up
         mg.mgpcg_gs_sweep(prob.h, 0, r, z, layout=mg.INTERNAL, stream=stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # The launches are queued behind a short spin kernel, so that they run
-    # back to back: otherwise a host slower than one launch per ~14 us would
-    # add its gaps to the measured kernel time.  The spin is sized from a
-    # timed 2^20-cycle spin to ~30 ms, far more than the host needs to queue,
-    # and bounded to 1e6..1e8 cycles (at most 1 s even at a 100 MHz counter).
-    e0.record(stream)
-    torch.cuda._sleep(1 << 20)
-    e1.record(stream)
-    e1.synchronize()
-    cycles_per_ms = (1 << 20) / max(e0.elapsed_time(e1), 1e-3)
-    torch.cuda._sleep(int(min(max(30.0 * cycles_per_ms, 1e6), 1e8)))
+    queue_spin(torch, stream)
     e0.record(stream)
     for _ in range(reps):
         for k in range(8):
@@ -177,6 +183,41 @@ def dominant_kernel(torch, mg, prob, reps=40):
     e1.synchronize()
     launches = reps * 8
     return e0.elapsed_time(e1) * 1e-3 / launches, launches
+
+
+def standalone(torch, mg, prob, reps=20):
+    """The standalone level-0 SpMV (mgpcg_spmv) and symmetric coloured
+    sweep (mgpcg_gs_sweep: 15 pass launches from a nonzero z), each timed with
+    HIP events on the stream the library launches them on, queued behind a
+    short spin so that the launches run back to back; the method's bytes per
+    call against 8 TB/s."""
+    from paper_2304_08232_amd import perfmodel
+    n = prob.n(0)
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    z = torch.rand(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, call, nbytes in (
+            ("spmv", lambda: mg.mgpcg_spmv(prob.h, 0, x, y, layout=mg.INTERNAL, stream=stream),
+             perfmodel.spmv_bytes(GRID)),
+            ("sym_sweep", lambda: mg.mgpcg_gs_sweep(prob.h, 0, x, z, layout=mg.INTERNAL, stream=stream),
+             perfmodel.sym_sweep_bytes(GRID))):
+        for _ in range(3):
+            call()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        queue_spin(torch, stream)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        out[name] = {"us": round(t * 1e6, 2), "alg_bytes": int(nbytes),
+                     "alg_gbs": round(nbytes / t / 1e9, 1),
+                     "frac_of_peak": round(nbytes / t / 1e9 / perfmodel.HBM_PEAK_GBS, 4)}
+    out["grid"] = list(GRID)
+    return out
 
 
 def cpu_baseline(reps=10):
@@ -550,6 +591,8 @@ def main():
     per_launch_bytes = perfmodel.sweep_pass_bytes(GRID)
     t_launch, launches = dominant_kernel(torch, mg, prob)
     log(f"dominant kernel: {t_launch * 1e6:.2f} us per colour pass over {launches} launches")
+    alone = standalone(torch, mg, prob)
+    log(f"standalone: spmv {alone['spmv']['us']} us, symmetric sweep {alone['sym_sweep']['us']} us")
     if args.only_kernel:
         # three eager iterations, so that counter runs also see the CG kernels
         prob.set_graph_mode(False)
@@ -626,6 +669,8 @@ def main():
                      "frac_of_one_shot_read": round(one_shot_us / (t_launch * 1e6), 4),
                      "alg_bytes_per_launch": int(per_launch_bytes),
                      "avg_launch_us": round(t_launch * 1e6, 3)},
+        # the level-0 SpMV and symmetric sweep on their own (128^3 config)
+        "standalone": alone,
     }
     if not args.no_extensions:
         del b, x

@@ -444,11 +444,28 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const T *__restrict_
     y[gid] = row_sum<T, R, 0u, true, CF>(val, col, dcol, sb, n, i, x, v, d);
 }
 
+template <int R, int CF, bool PQ>
+__global__ void k_spmv_pq(int64_t n, const double *__restrict__ val, const int32_t *__restrict__ col,
+                          const int8_t *__restrict__ dcol, const int32_t *__restrict__ dbase,
+                          const double *__restrict__ p, double *__restrict__ q, const Seg *__restrict__ tab,
+                          double *__restrict__ partials, const int *__restrict__ done, int spc);
+
 template <typename T>
 hipError_t launch_spmv(const mgpcg_problem *P, int level, const T *val, const T *x, T *y, hipStream_t s) {
     const Level &L = P->lev[level];
     int64_t work = L.n * P->R;
     if (work == 0) return hipSuccess;
+    if constexpr (sizeof(T) == 8) {
+        // level 0, one grid, one rhs: the CG product kernel without its dot
+        if (level == 0 && P->G == 1 && P->R == 1 && (const void *)val == (const void *)L.val64) {
+#define MG_SPMV0(CFV)                                                                                   \
+    k_spmv_pq<1, CFV, false><<<P->n_red[0], kBlock, 0, s>>>(L.n, L.val64, L.col, L.dcol, L.dbase, x, y,    \
+                                                            P->red_tab[0], nullptr, nullptr, P->spc);
+            if (L.cf == 2) { MG_SPMV0(2) } else if (L.cf == 1) { MG_SPMV0(1) } else { MG_SPMV0(0) }
+#undef MG_SPMV0
+            return hipGetLastError();
+        }
+    }
     const CoffTable ct = coff_table(L);
 #define MG_SPMV(CFV)                                                                                   \
     MG_DISPATCH_R(P->R, (k_spmv<T, RR, CFV><<<nblocks(work), kBlock, 0, s>>>(L.n, val, L.col, L.dcol, L.dbase, \
@@ -1821,7 +1838,9 @@ __global__ __launch_bounds__(kBlock) void k_flush_x(double *__restrict__ x, cons
 // occupancy, and more loads in flight per wave took it from 100 to 92 us at
 // 128^3.  (The colour passes, whose 1024 workgroups fit in one round at the
 // higher occupancy, and the LDS-staged R >= 4 product became slower.)
-template <int R, int CF>
+// PQ = false: q = A p only (the standalone level-0 SpMV, one grid, one rhs),
+// with the same loads and sums as inside the solve.
+template <int R, int CF, bool PQ = true>
 __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__restrict__ val,
                                                     const int32_t *__restrict__ col,
                                                     const int8_t *__restrict__ dcol,
@@ -1881,6 +1900,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
                     s = row_sum<double, R, 0u, true, CF>(val, col, dcol, sb, n, i, p, v, d);
                 }
                 q[i * R + v] = s;
+                if constexpr (!PQ) continue;
                 if constexpr (R == 1) acc = p[i * R + v] * s;
                 else acc += p[i * R + v] * s;
             }
@@ -1900,7 +1920,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
             __syncthreads();  // the next entry overwrites sv
         }
     }
-    store_partial<R>(acc, blk, partials);
+    if constexpr (PQ) store_partial<R>(acc, blk, partials);
 }
 
 // r -= alpha q; partial ||r||^2 (the x update x += alpha p is deferred to

@@ -58,4 +58,17 @@ def sweep_pass_bytes(dims, mg_dtype="fp64"):
     return (mb * nnz + 3 * vb * n) / 8.0
 
 
+def spmv_bytes(dims):
+    """Bytes of one standalone FP64 SpMV y = A x at level 0."""
+    n, nnz = level_sizes(dims, 1)[0]
+    return 12 * nnz + 16 * n
+
+
+def sym_sweep_bytes(dims):
+    """Bytes of one standalone FP64 symmetric sweep (forward and backward
+    directional sweeps) at level 0."""
+    n, nnz = level_sizes(dims, 1)[0]
+    return 2 * (12 * nnz + 24 * n)
+
+
 HBM_PEAK_GBS = 8000.0

@@ -38,6 +38,9 @@ def test_small_problem_and_standalone_kernels():
     assert abs((2 * nnz + 4 * n) / 1e6 - 119.9) < 0.1
     # the standalone SpMV: 702.5 MB, 111.5 MFLOP
     assert abs((12 * nnz + 16 * n) / 1e6 - 702.5) < 0.1
+    assert abs(perfmodel.spmv_bytes((128, 128, 128)) / 1e6 - 702.5) < 0.1
+    # a symmetric sweep is two directional sweeps: 1438.4 MB
+    assert abs(perfmodel.sym_sweep_bytes((128, 128, 128)) / 1e6 - 1438.4) < 0.1
 
 
 def test_batched_sum_and_rhs_scaling():
