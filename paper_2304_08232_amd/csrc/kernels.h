@@ -61,10 +61,13 @@ hipError_t launch_fill_u(unsigned *p, int64_t n, unsigned v, hipStream_t s);
 // CG kernels on level 0 (FP64, internal layout), with per-system scalars
 hipError_t launch_init_residual(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s);
+// FP32 V-cycle: widen its level-0 z into P->z and form <r, z> in one pass
+hipError_t launch_cast_dot_rz(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_finalize_rz(const mgpcg_problem *P, hipStream_t s);  // rho from the fused partials
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s);
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s);
-hipError_t launch_update_r(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s);
+// r32 (FP32 V-cycle, may be NULL): also store the new r narrowed there
+hipError_t launch_update_r(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s, float *r32 = nullptr);
 hipError_t launch_flush_x(const mgpcg_problem *P, hipStream_t s);  // x += pending alpha p, after the last iteration
 
 hipError_t launch_theta_grad(const double *lam, const double *x, const double *theta, double *grad,

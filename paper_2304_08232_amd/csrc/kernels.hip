@@ -1755,6 +1755,33 @@ __global__ __launch_bounds__(kBlock) void k_dot_rz(const double *__restrict__ r,
     store_partial<R>(acc, blk, partials);
 }
 
+// FP32 V-cycle: z = (double) z32 and the partial <r, z> in one pass (the
+// widening is exact, so the products and their order are k_dot_rz's on the
+// widened z; one pass over the vectors less than the cast and the dot)
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_cast_dot_rz(const double *__restrict__ r, const float *__restrict__ z32,
+                                                        double *__restrict__ z, const Seg *__restrict__ tab,
+                                                        int64_t nrows, double *__restrict__ partials,
+                                                        const int *__restrict__ done) {
+    MG_ARGS_FIRST("s"(r), "s"(z32), "s"(z), "s"(tab), "s"(nrows), "s"(partials), "s"(done), "s"(gridDim.x));
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const Seg e = vec_seg(tab, blk, nrows, kVecRows * kBlock / R);
+    if (done && grid_done<R>(done, e.grid)) return;
+    const int v = threadIdx.x % R;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < kVecRows; ++u) {
+        const int rl = threadIdx.x / R + u * (kBlock / R);
+        if (rl < e.count) {
+            const int64_t o = (e.row0 + rl) * R + v;
+            const double zo = (double)z32[o];
+            z[o] = zo;
+            acc += r[o] * zo;
+        }
+    }
+    store_partial<R>(acc, blk, partials);
+}
+
 // The vector kernels' loads of one thread: its kVecRows rows (a row past the
 // chunk's end is read as its last row, and not stored).  The values are
 // consumed by an empty asm statement that runs on every path, so that the
@@ -1926,12 +1953,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
 // r -= alpha q; partial ||r||^2 (the x update x += alpha p is deferred to
 // the next k_update_p, or to k_flush_x after the last iteration)
 // (converged systems: as in k_update_p; their r is not written)
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_update_r(double *__restrict__ r, const double *__restrict__ q,
-                                                     const Seg *__restrict__ tab, int64_t nrows,
-                                                     double *__restrict__ partials, Scalars sc) {
-    MG_ARGS_FIRST("s"(r), "s"(q), "s"(tab), "s"(nrows), "s"(partials), "s"(sc.alpha), "s"(sc.done),
-                  "s"(gridDim.x));
+// W32 (FP32 V-cycle): the new r is also stored narrowed into r32, the next
+// V-cycle's level-0 right-hand side, instead of a separate cast pass.
+template <int R, bool W32>
+__device__ __forceinline__ void update_r_body(double *__restrict__ r, const double *__restrict__ q,
+                                              const Seg *__restrict__ tab, int64_t nrows,
+                                              double *__restrict__ partials, const Scalars &sc,
+                                              float *__restrict__ r32) {
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const Seg e = vec_seg(tab, blk, nrows, kVecRows * kBlock / R);
     if (tab && grid_done<R>(sc.done, e.grid)) return;
@@ -1951,12 +1979,32 @@ __global__ __launch_bounds__(kBlock) void k_update_r(double *__restrict__ r, con
                 if (rl < e.count) {
                     const double ri = val[0][u] - alpha * val[1][u];
                     r[o[u]] = ri;
+                    if constexpr (W32) r32[o[u]] = (float)ri;
                     acc += ri * ri;
                 }
             }
         }
     }
     store_partial<R>(acc, blk, partials);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_update_r(double *__restrict__ r, const double *__restrict__ q,
+                                                     const Seg *__restrict__ tab, int64_t nrows,
+                                                     double *__restrict__ partials, Scalars sc) {
+    MG_ARGS_FIRST("s"(r), "s"(q), "s"(tab), "s"(nrows), "s"(partials), "s"(sc.alpha), "s"(sc.done),
+                  "s"(gridDim.x));
+    update_r_body<R, false>(r, q, tab, nrows, partials, sc, nullptr);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_update_r32(double *__restrict__ r, const double *__restrict__ q,
+                                                       const Seg *__restrict__ tab, int64_t nrows,
+                                                       double *__restrict__ partials, Scalars sc,
+                                                       float *__restrict__ r32) {
+    MG_ARGS_FIRST("s"(r), "s"(q), "s"(tab), "s"(nrows), "s"(partials), "s"(sc.alpha), "s"(sc.done),
+                  "s"(gridDim.x), "s"(r32));
+    update_r_body<R, true>(r, q, tab, nrows, partials, sc, r32);
 }
 
 // One workgroup per grid: sum the grid's partials in a fixed order, then
@@ -2145,6 +2193,15 @@ hipError_t launch_dot_rz(const mgpcg_problem *P, hipStream_t s) {
     if (e != hipSuccess) return e;
     return finalize<kRz>(P, 1, 0.0, 0, s);
 }
+hipError_t launch_cast_dot_rz(const mgpcg_problem *P, hipStream_t s) {
+    const bool one = P->G == 1;
+    MG_DISPATCH_R(P->R, (k_cast_dot_rz<RR><<<P->n_red[1], kBlock, 0, s>>>(
+                            P->r, (const float *)P->lev[0].z, P->z, one ? nullptr : P->red_tab[1], P->lev[0].n,
+                            P->sc.partials, one ? nullptr : P->sc.done)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize<kRz>(P, 1, 0.0, 0, s);
+}
 hipError_t launch_finalize_rz(const mgpcg_problem *P, hipStream_t s) { return finalize<kRz>(P, 2, 0.0, 0, s); }
 hipError_t launch_update_p(const mgpcg_problem *P, hipStream_t s) {
     const bool one = P->G == 1;
@@ -2173,10 +2230,15 @@ hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     if (e != hipSuccess) return e;
     return finalize<kPq>(P, 0, 0.0, 0, s);
 }
-hipError_t launch_update_r(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s) {
+hipError_t launch_update_r(const mgpcg_problem *P, double tol, int hist_cap, hipStream_t s, float *r32) {
     const bool one = P->G == 1;
-    MG_DISPATCH_R(P->R, (k_update_r<RR><<<P->n_red[1], kBlock, 0, s>>>(P->r, P->q, one ? nullptr : P->red_tab[1],
-                                                                       P->lev[0].n, P->sc.partials, P->sc)));
+    if (r32) {
+        MG_DISPATCH_R(P->R, (k_update_r32<RR><<<P->n_red[1], kBlock, 0, s>>>(
+                                P->r, P->q, one ? nullptr : P->red_tab[1], P->lev[0].n, P->sc.partials, P->sc, r32)));
+    } else {
+        MG_DISPATCH_R(P->R, (k_update_r<RR><<<P->n_red[1], kBlock, 0, s>>>(
+                                P->r, P->q, one ? nullptr : P->red_tab[1], P->lev[0].n, P->sc.partials, P->sc)));
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return finalize<kRr>(P, 1, tol, hist_cap, s);

@@ -912,27 +912,42 @@ hipError_t vcycle_lex(const mgpcg_problem *P, const double *r0, double *z0, hipS
 }
 
 // z = M^{-1} r on the CG vectors (FP64, internal layout)
+// fused (FP32 V-cycle inside the CG iteration): the level-0 FP32 r was
+// already stored by the previous residual update (or after the initial
+// residual), and z is left in the level-0 FP32 workspace for a kernel that
+// widens it and forms <r, z> in the same pass
 hipError_t precondition(const mgpcg_problem *P, const double *r, double *z, const int *done, hipStream_t s,
-                        double *rzp = nullptr) {
+                        double *rzp = nullptr, bool fused = false) {
     if (P->smoother == MGPCG_SMOOTHER_SEQUENTIAL) return vcycle_lex(P, r, z, s);
     if (P->mg_dtype == MGPCG_FP64) return vcycle<double>(P, r, z, done, s, rzp);
     const Level &L0 = P->lev[0];
     hipError_t e;
     const int64_t n = L0.n * P->R;
-    if ((e = launch_cast_d2f(r, (float *)L0.r, n, s)) != hipSuccess) return e;
+    if (!fused && (e = launch_cast_d2f(r, (float *)L0.r, n, s)) != hipSuccess) return e;
     if ((e = vcycle<float>(P, (const float *)L0.r, (float *)L0.z, done, s)) != hipSuccess) return e;
-    return launch_cast_f2d((const float *)L0.z, z, n, s);
+    return fused ? hipSuccess : launch_cast_f2d((const float *)L0.z, z, n, s);
+}
+
+// the FP32 V-cycle's right-hand side and correction are narrowed and widened
+// inside the CG kernels (not for the sequential smoother, which is FP64)
+static bool fused_fp32(const mgpcg_problem *P) {
+    return P->mg_dtype == MGPCG_FP32 && P->smoother != MGPCG_SMOOTHER_SEQUENTIAL;
 }
 
 hipError_t cg_iteration(mgpcg_problem *P, double tol, hipStream_t s) {
     hipError_t e;
-    // rho = <r, z>: accumulated by the level-0 post-smoother when fuse_rz
-    if ((e = precondition(P, P->r, P->z, P->sc.done, s, P->fuse_rz ? P->sc.partials : nullptr)) != hipSuccess)
+    // rho = <r, z>: accumulated by the level-0 post-smoother when fuse_rz;
+    // with the FP32 V-cycle, formed while its z is widened
+    const bool f32 = fused_fp32(P);
+    if ((e = precondition(P, P->r, P->z, P->sc.done, s, P->fuse_rz ? P->sc.partials : nullptr, f32)) !=
+        hipSuccess)
         return e;
-    if ((e = P->fuse_rz ? launch_finalize_rz(P, s) : launch_dot_rz(P, s)) != hipSuccess) return e;
+    if ((e = P->fuse_rz ? launch_finalize_rz(P, s) : f32 ? launch_cast_dot_rz(P, s) : launch_dot_rz(P, s)) !=
+        hipSuccess)
+        return e;
     if ((e = launch_update_p(P, s)) != hipSuccess) return e;
     if ((e = launch_spmv_pq(P, s)) != hipSuccess) return e;
-    return launch_update_r(P, tol, P->hist_cap, s);
+    return launch_update_r(P, tol, P->hist_cap, s, f32 ? (float *)P->lev[0].r : nullptr);
 }
 
 // ------------------------------------------------------- argument helpers
@@ -1588,6 +1603,9 @@ mgpcg_status mgpcg_pcg_solve(mgpcg_problem *p, const double *b, double *x, int m
     HIP_TRY(launch_fill_d(p->hist, (int64_t)S * p->hist_cap, 0.0, s));
     HIP_TRY(launch_fill_d(p->p, n, 0.0, s));
     HIP_TRY(launch_init_residual(p, s));
+    // the first FP32 V-cycle's right-hand side (later ones are stored by the
+    // residual updates)
+    if (fused_fp32(p)) HIP_TRY(launch_cast_d2f(p->r, (float *)p->lev[0].r, p->lev[0].n * p->R, s));
 
     if (p->use_graph && !p->iter_graph && max_iters > 0) {
         if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
