@@ -450,12 +450,34 @@ __global__ void k_spmv_pq(int64_t n, const double *__restrict__ val, const int32
                           const double *__restrict__ p, double *__restrict__ q, const Seg *__restrict__ tab,
                           double *__restrict__ partials, const int *__restrict__ done, int spc);
 
+template <int R, bool PQ>
+__global__ void k_spmv_box(const double *__restrict__ val, const double *__restrict__ p, double *__restrict__ q,
+                           double *__restrict__ partials, BoxGeo g);
+
+// the box-tiled level-0 product (P->box_ok); PQ: with the <p, q> partials
+template <bool PQ>
+hipError_t launch_spmv_box(const mgpcg_problem *P, const double *p, double *q, hipStream_t s) {
+    const double *val = P->lev[0].val64;
+    double *parts = PQ ? P->sc.partials : nullptr;
+    switch (P->R) {
+        case 4: k_spmv_box<4, PQ><<<P->n_box, kBlock, 0, s>>>(val, p, q, parts, P->box); break;
+        case 8: k_spmv_box<8, PQ><<<P->n_box, kBlock, 0, s>>>(val, p, q, parts, P->box); break;
+        case 16: k_spmv_box<16, PQ><<<P->n_box, kBlock, 0, s>>>(val, p, q, parts, P->box); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_spmv(const mgpcg_problem *P, int level, const T *val, const T *x, T *y, hipStream_t s) {
     const Level &L = P->lev[level];
     int64_t work = L.n * P->R;
     if (work == 0) return hipSuccess;
     if constexpr (sizeof(T) == 8) {
+        // level 0, one grid, R >= 4 on a box-tiled geometry: the CG product
+        // kernel without its dot
+        if (level == 0 && P->box_ok && (const void *)val == (const void *)L.val64)
+            return launch_spmv_box<false>(P, x, y, s);
         // level 0, one grid, one rhs: the CG product kernel without its dot
         if (level == 0 && P->G == 1 && P->R == 1 && (const void *)val == (const void *)L.val64) {
 #define MG_SPMV0(CFV)                                                                                   \
@@ -1954,6 +1976,108 @@ __global__ __launch_bounds__(kBlock) void k_spmv_pq(int64_t n, const double *__r
     if constexpr (PQ) store_partial<R>(acc, blk, partials);
 }
 
+// q = A p and partial <p, q>, one grid, R >= kPairR right-hand sides, all
+// level-0 extents even and nx a multiple of 2 box_run(R) (BoxGeo).  A
+// workgroup owns BX = box_run(R) consecutive half-points in x at one (Y, Z)
+// (16, 8, 4 at R = 4, 8, 16, so that its 8 BX rows fill kBlock threads): a
+// 2BX x 2 x 2 box of fine points, BX rows of each of the 8 colours.  It stages
+// p on the box and its one-point halo ((2BX+2) x 4 x 4 points) in LDS, and its
+// rows read their 27 neighbours there: about 5 staged loads per row instead of
+// 27 gathers through the texture unit, which bounds the table-driven product
+// at R >= 4.  The rows' operator values are staged as in the other paired
+// kernels.  Every right-hand side's sum takes row_sum2's slot order and
+// operations (a missing neighbour has value 0 and is skipped, so the halo
+// outside the grid holds zeros), so q is bit-identical to the table-driven
+// product; only the grouping of the <p, q> partials differs.  PQ = false:
+// q = A p only (the standalone level-0 product).
+template <int R, bool PQ>
+__global__ __launch_bounds__(kBlock) void k_spmv_box(const double *__restrict__ val, const double *__restrict__ p,
+                                                     double *__restrict__ q, double *__restrict__ partials,
+                                                     BoxGeo g) {
+    static_assert(R >= kPairR, "two right-hand sides per lane");
+    constexpr int LN = pass_lanes(R), BX = box_run(R), RWS = 8 * BX, BS = kBlock;
+    constexpr int TX = 2 * BX + 2, TY = 4, TZ = 4, TP = TX * TY * TZ;
+    typedef double V2 __attribute__((ext_vector_type(2)));
+    constexpr int NP = (TP + RWS - 1) / RWS, NV = (kW * RWS + BS - 1) / BS;
+    // (padded to whole rounds of the staging loops, whose stores are then
+    // unconditional: a store under a branch drags its load into the branch)
+    __shared__ V2 tile[NP * RWS * LN];  // point-major: tile[pt * LN + w] = rhs 2w, 2w+1
+    __shared__ double sv[NV * BS];      // sv[s * RWS + row]
+    // Boxes in slabs of 8 half-lines in y: x fastest, then y within the slab,
+    // then z, then the slab.  The boxes that share halo points with a box are
+    // then at most 8 * nxb workgroups apart, and an XCD (a contiguous range of
+    // logical blocks) works through one slab at a time, so that its halo reads
+    // hit its L2.  (With y before z, the z-neighbours of a box were hy * nxb
+    // blocks away, out of the L2, and p was read 2.7 times from memory.)
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int xb = b % g.nxb, t = b / g.nxb;
+    const int hz = g.nz >> 1, slab = t / (kBoxSlab * hz);
+    const int sy = min(kBoxSlab, g.hy - kBoxSlab * slab), rem = t - slab * kBoxSlab * hz;
+    const int Y = kBoxSlab * slab + rem % sy, Z = rem / sy;
+    const int x0 = 2 * BX * xb - 1, y0 = 2 * Y - 1, z0 = 2 * Z - 1;  // fine origin of the tile
+    const int64_t run = ((int64_t)Z * g.hy + Y) * g.hx + BX * xb;   // the run's offset within a class
+    const int w = threadIdx.x % LN, ps = threadIdx.x / LN;
+    // All loads are issued before any is used, unconditionally: a point
+    // outside the grid (or past the tile) loads from its clamped position and
+    // is replaced by zero afterwards.  (A load under a divergent branch is
+    // waited for at the end of the branch, one round trip per load.)
+    V2 pv[NP];
+    bool inside[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int pt = min(ps + RWS * k, TP - 1);
+        const int tx = pt % TX, ty = (pt / TX) % TY, tz = pt / (TX * TY);
+        const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+        inside[k] = (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny && (unsigned)z < (unsigned)g.nz;
+        const int xc = min(max(x, 0), g.nx - 1), yc = min(max(y, 0), g.ny - 1), zc = min(max(z, 0), g.nz - 1);
+        const int pc = (xc & 1) | (yc & 1) << 1 | (zc & 1) << 2;
+        const int64_t i = (int64_t)(pc ^ g.flip) * g.nh + ((int64_t)(zc >> 1) * g.hy + (yc >> 1)) * g.hx + (xc >> 1);
+        pv[k] = *(const V2 *)(p + i * R + 2 * w);
+    }
+    double av[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const int e = min((int)threadIdx.x + u * BS, kW * RWS - 1);  // e = s * RWS + class * BX + j
+        const int s = e / RWS, c = (e % RWS) / BX, j = e % BX;
+        av[u] = ld<true>(val + ell_index(s, (int64_t)(c ^ g.flip) * g.nh + run + j));
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) tile[(ps + RWS * k) * LN + w] = inside[k] ? pv[k] : V2{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < NV; ++u) sv[threadIdx.x + u * BS] = av[u];
+    __syncthreads();
+    // row ps: class c = ps / BX, half-point BX xb + j; its fine point in the tile
+    const int c = ps / BX, j = ps % BX;
+    const int pt0 = (((c >> 2) + 1) * TY + ((c >> 1) & 1) + 1) * TX + 2 * j + (c & 1) + 1;
+    // Each right-hand side's sum in slot order, the two side by side, nine
+    // slots' LDS reads issued at a time; a zero value (a missing neighbour)
+    // leaves the sum as it is, by a select rather than a branch, so that no
+    // read waits behind the test of another.
+    double s2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int t0 = 0; t0 < kW; t0 += 9) {
+        double a[9];
+        V2 xv[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int t = t0 + k;
+            a[k] = sv[t * RWS + ps];
+            xv[k] = tile[(pt0 + ((t / 9 - 1) * TY + (t / 3 % 3 - 1)) * TX + (t % 3 - 1)) * LN + w];
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double n0 = s2[0] + a[k] * xv[k].x, n1 = s2[1] + a[k] * xv[k].y;
+            s2[0] = a[k] != 0.0 ? n0 : s2[0];
+            s2[1] = a[k] != 0.0 ? n1 : s2[1];
+        }
+    }
+    st_lanes(q + ((int64_t)(c ^ g.flip) * g.nh + run + j) * R + 2 * w, s2);
+    if constexpr (PQ) {
+        const V2 pc2 = tile[pt0 * LN + w];
+        store_partial2<R>(pc2.x * s2[0], pc2.y * s2[1], b, partials);
+    }
+}
+
 // r -= alpha q; partial ||r||^2 (the x update x += alpha p is deferred to
 // the next k_update_p, or to k_flush_x after the last iteration)
 // (converged systems: as in k_update_p; their r is not written)
@@ -2158,11 +2282,13 @@ __global__ __launch_bounds__(kBlock) void k_fold(const double *__restrict__ part
 }
 
 template <int KIND>
-static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hist_cap, hipStream_t s) {
+static hipError_t finalize(const mgpcg_problem *P, int table, double tol, int hist_cap, hipStream_t s,
+                           int nparts = 0) {
     const int *gb = P->red_gb[table];
     const double *parts = P->sc.partials;
     // partials of one grid: the workgroups of the producing kernel(s)
-    int nblk = table == 2 ? (int)P->rz_off[8] : P->n_red[table];
+    // (nparts > 0: a kernel outside the tables, one grid)
+    int nblk = nparts > 0 ? nparts : table == 2 ? (int)P->rz_off[8] : P->n_red[table];
     if (P->fold) {
         MG_DISPATCH_R(P->R, (k_fold<RR><<<kFoldBlocks, kBlock, 0, s>>>(P->sc.partials, nblk, P->fold)));
         parts = P->fold;
@@ -2224,6 +2350,11 @@ hipError_t launch_flush_x(const mgpcg_problem *P, hipStream_t s) {
 }
 hipError_t launch_spmv_pq(const mgpcg_problem *P, hipStream_t s) {
     const Level &L = P->lev[0];
+    if (P->box_ok) {
+        hipError_t e = launch_spmv_box<true>(P, P->p, P->q, s);
+        if (e != hipSuccess) return e;
+        return finalize<kPq>(P, 0, 0.0, 0, s, P->n_box);
+    }
 #define MG_SPMVPQ(CFV)                                                                                 \
     MG_DISPATCH_R(P->R, (k_spmv_pq<RR, CFV><<<P->n_red[0], kBlock, 0, s>>>(                             \
                             L.n, L.val64, L.col, L.dcol, L.dbase, P->p, P->q, P->red_tab[0], P->sc.partials, \

@@ -618,6 +618,31 @@ mgpcg_status build_hierarchy(mgpcg_problem *P, const double *theta, hipStream_t 
             ST_TRY(dalloc(&P->red_gb[2], 2));
             HIP_TRY(set_rz_layout(P, s));
         }
+        // box-tiled product (k_spmv_box): one grid of even extents, two
+        // right-hand sides per lane; one workgroup per box of box_run(R)
+        // half-points in x at one (Y, Z), i.e. 8 * box_run(R) rows
+        {
+            const int nx = P->dims0[0], ny = P->dims0[1], nz = P->dims0[2];
+            const int bx = R >= kPairR ? box_run(R) : 1;
+            P->box_ok = G == 1 && R >= kPairR && L0.ncol == 8 && nx % (2 * bx) == 0 && ny % 2 == 0 && nz % 2 == 0;
+            if (P->box_ok) {
+                mg::BoxGeo &bg = P->box;
+                bg.nx = nx;
+                bg.ny = ny;
+                bg.nz = nz;
+                bg.hx = nx / 2;
+                bg.hy = ny / 2;
+                bg.nxb = nx / (2 * bx);
+                bg.nh = (int32_t)(L0.n / 8);
+                bg.flip = P->colour_order ? 7 : 0;
+                Colouring C(nx, ny, nz, P->colour_order);
+                for (int pc = 0; pc < 8; ++pc)
+                    if (L0.coff[C.colour(pc & 1, (pc >> 1) & 1, pc >> 2)] != (int64_t)(pc ^ bg.flip) * bg.nh)
+                        return fail(MGPCG_ERR_DIMS, "internal: box geometry does not match the colour ranges");
+                P->n_box = (int)(L0.n / (8 * bx));
+                max_blocks = std::max<int64_t>(max_blocks, P->n_box);
+            }
+        }
         const int64_t n0 = L0.n * R;
         ST_TRY(dalloc(&P->x, n0));
         ST_TRY(dalloc(&P->r, n0));

@@ -42,6 +42,10 @@ constexpr int pass_block(bool streamed) { return streamed ? 256 : 64; }
 constexpr int kPairR = 4;
 constexpr int pass_lanes(int R) { return R >= kPairR ? R / 2 : R; }
 constexpr int pass_rows(bool streamed, int R) { return pass_block(streamed) / pass_lanes(R); }
+// box-tiled CG product (R >= kPairR): half-points in x per box, so that the
+// box's 8 * box_run(R) rows fill a kBlock-thread workgroup
+constexpr int box_run(int R) { return kBlock / 8 / pass_lanes(R); }
+constexpr int kBoxSlab = 8;  // half-lines in y per slab of the box order
 // threads of the single-workgroup coarsest-level kernel; it is used only when
 // every colour of that level has at most this many rows
 constexpr int kTailBlock = 512;
@@ -188,6 +192,21 @@ struct CoarseArgs {
     long long spin_limit;
 };
 
+// Level-0 geometry of the box-tiled CG product (one grid, R >= kPairR, all
+// extents even, nx a multiple of 2 box_run(R)).  Every colour then has nh
+// rows, and the points of parity class pc = (x&1) + 2(y&1) + 4(z&1) (colour
+// pc, or 7 - pc = pc ^ 7 under colour order 1) start at row (pc ^ flip) * nh;
+// within a class, rows follow the half-grid coordinates (x>>1, y>>1, z>>1),
+// x fastest.  (Arithmetic, not a table: a table indexed per lane would be
+// read from the kernel arguments by a dependent vector load.)
+struct BoxGeo {
+    int nx, ny, nz;  // fine extents
+    int hx, hy;      // half extents in x and y
+    int nxb;         // boxes per half-line (hx / box_run(R))
+    int32_t nh;      // rows per colour
+    int flip;        // 0 or 7
+};
+
 struct Scalars {  // per-system CG state, device arrays of S entries
     double *rho, *rho_old, *alpha, *beta, *nr0, *pq;
     double *apend;       // alpha of the x update still pending (0: none)
@@ -232,6 +251,10 @@ struct mgpcg_problem {
     int *red_gb[3] = {nullptr, nullptr, nullptr};
     bool fuse_rz = false;
     int64_t rz_off[9] = {};
+    // box-tiled CG product (k_spmv_box) and its workgroup count
+    bool box_ok = false;
+    mg::BoxGeo box{};
+    int n_box = 0;
 
     // CG vectors, level 0, internal layout, n0*R doubles
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr;

@@ -473,6 +473,37 @@ def test_multi_rhs_paired_lanes_both_widths(mg, nrhs, order):
     for v in (0, nrhs - 1):
         xo, ho, ito, _ = o.pcg(B[v * n:(v + 1) * n], max_iters=8)
         hist_ok(h[v, :ito], ho)
+    Y = host(p.spmv(dev(B)))
+    for v in (0, nrhs - 1):
+        np.testing.assert_array_equal(Y[v * n:(v + 1) * n], o.spmv(B[v * n:(v + 1) * n]), err_msg=f"rhs {v}")
+    p.check()
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("nrhs", [4, 8, 16])
+@pytest.mark.parametrize("dims,levels", [((16, 2, 2), 2), ((48, 6, 10), 2), ((32, 12, 4), 3), ((64, 4, 6), 2),
+                                         ((20, 8, 8), 3)])
+def test_multi_rhs_box_product(mg, dims, levels, nrhs, order):
+    # One grid with R >= 4 and even extents, nx a multiple of the box length
+    # (8, 16, 32 fine points at 16, 8, 4 right-hand sides): the CG product
+    # stages p on boxes of 2x2 half-lines plus a one-point halo in LDS.  The
+    # product must equal the oracle's bit for bit on every right-hand side
+    # (boxes at every face and edge, thin extents of 2), and a short solve
+    # must follow the oracle's history.  Shapes whose nx is not a multiple
+    # ((16, 2, 2) and (48, 6, 10) at 4 rhs, (20, 8, 8) always) take the
+    # table-driven product, for contrast.
+    o = Oracle(*dims, levels=levels, colour_order=order)
+    n = o.n()
+    B = inputs.multi_rhs(47, nrhs, n)
+    print(f"box product {dims} nrhs={nrhs} order={order}", flush=True)
+    p = mg.Problem(dims, levels=levels, nrhs=nrhs, colour_order=order)
+    Y = host(p.spmv(dev(B)))
+    for v in range(nrhs):
+        np.testing.assert_array_equal(Y[v * n:(v + 1) * n], o.spmv(B[v * n:(v + 1) * n]), err_msg=f"rhs {v}")
+    x, h, its, st = p.solve(dev(B), max_iters=6)
+    for v in (0, nrhs // 2, nrhs - 1):
+        xo, ho, ito, _ = o.pcg(B[v * n:(v + 1) * n], max_iters=6)
+        hist_ok(h[v, :ito], ho)
     p.check()
 
 
