@@ -96,6 +96,12 @@ def test_multi_rhs_16_128cubed(mg):
     o = Oracle(*dims)
     for v in (0, 9, 15):
         np.testing.assert_array_equal(Z[v * n:(v + 1) * n], o.vcycle(B[v * n:(v + 1) * n]))
+    # the box-tiled product of the solve, in the launch configuration the
+    # solve uses, bit for bit on three right-hand sides
+    Y = host(p.spmv(dev(B)))
+    for v in (0, 9, 15):
+        np.testing.assert_array_equal(Y[v * n:(v + 1) * n], o.spmv(B[v * n:(v + 1) * n]))
+    del Y
     X, H, its, st = p.solve(dev(B), max_iters=400, tol=1e-9)
     assert st == mg.OK
     Xg = host(X)
