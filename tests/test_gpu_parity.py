@@ -224,9 +224,12 @@ def test_pcg_nonzero_x0(mg):
     assert np.linalg.norm(host(x) - xo) <= 1e-12 * np.linalg.norm(xo)
 
 
-def test_graph_and_eager_identical_and_deterministic(mg):
-    p = mg.Problem((16, 16, 16))
-    b = p.make_rhs_ones()
+@pytest.mark.parametrize("nrhs", [1, 4, 16])
+def test_graph_and_eager_identical_and_deterministic(mg, nrhs):
+    # (4 and 16 right-hand sides: the box-tiled product and the folded
+    # partials in the same comparison)
+    p = mg.Problem((16, 16, 16), nrhs=nrhs)
+    b = p.make_rhs_ones() if nrhs == 1 else dev(inputs.multi_rhs(51, nrhs, 16 ** 3))
     outs = []
     for mode in (1, 1, 0, 1):
         p.set_graph_mode(mode)
