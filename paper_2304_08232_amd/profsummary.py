@@ -406,9 +406,44 @@ def traffic_summary(t, cmd):
         f"({t['hbm_bytes_per_launch'] / 1e6:.2f} MB)"])
 
 
+def counters(dirs, match=None):
+    """{(kernel, grid): {counter: [values]}} over one or more --pmc runs"""
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                k = _short(r["Kernel_Name"])
+                if match and not re.search(match, k):
+                    continue
+                g = int(r.get("Grid_Size", r.get("Grid_Size_X", 0)))
+                vals[(k, g)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return vals
+
+
+def counters_summary(vals, cmd, gui_xcds=8, cus=256):
+    """Per kernel: dispatches and the mean of every counter per dispatch.  Where
+    GRBM_GUI_ACTIVE (summed over the XCDs) was taken, the busy fraction of
+    each per-CU unit counter (TA_TA_BUSY, TD_TD_BUSY, summed over the CUs) is
+    added: counter / cus / (GRBM_GUI_ACTIVE / xcds)."""
+    out = ["# rocprofv3 counter summary: mean per dispatch of every counter, by kernel",
+           f"# commands: {cmd}"]
+    for (k, g), cs in sorted(vals.items(), key=lambda kv: (-kv[0][1], kv[0][0])):
+        n = max(len(v) for v in cs.values())
+        mean = {c: sum(v) / len(v) for c, v in cs.items()}
+        parts = [f"{c}={m:.4g}" for c, m in sorted(mean.items())]
+        gui = mean.get("GRBM_GUI_ACTIVE")
+        if gui:
+            for c in ("TA_TA_BUSY", "TD_TD_BUSY"):
+                if c in mean:
+                    parts.append(f"{c}_frac={mean[c] / cus / (gui / gui_xcds):.2f}")
+        out.append(f"{k[:64]:64s} grid {g:9d} n {n:4d}  " + " ".join(parts))
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "pmc", "traffic", "traffic-all", "breakdown", "iteration-traffic"])
+    ap.add_argument("mode", choices=["trace", "pmc", "traffic", "traffic-all", "breakdown", "iteration-traffic",
+                                     "counters"])
     ap.add_argument("dir")
     ap.add_argument("args", nargs="*")
     ap.add_argument("--cmd", default="")
@@ -437,6 +472,9 @@ def main():
             with open(a.json, "w") as f:
                 json.dump(t, f, indent=1)
                 f.write("\n")
+        return 0
+    if a.mode == "counters":
+        print(counters_summary(counters([a.dir] + a.args, a.match), a.cmd))
         return 0
     if a.mode == "trace":
         print(trace_summary(a.dir, a.cmd, match=a.match))
